@@ -1,0 +1,199 @@
+"""ctypes front end of the CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the package smoke check and the CPU-baseline leg of the
+benchmark may import this module.  The product (the HIP library and its
+Python binding) never calls it.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+DIR_XY, DIR_ISO, DIR_X = 0, 1, 2
+START_REPLACE, START_DISTINCT = 0, 1
+EV_LIFT, EV_FROZEN, EV_WALL_X, EV_WALL_Y, EV_PSEUDO, EV_END = 1, 2, 3, 4, 5, 6
+CNT_LIFTS, CNT_FROZEN, CNT_WALLS, CNT_CHAINS, CNT_PSEUDO, CNT_NCOL = 0, 1, 2, 3, 4, 5
+
+
+class Params(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sigma", C.c_double), ("eta", C.c_double),
+                ("ell", C.c_double), ("cells", C.c_int32), ("chains_per_cell", C.c_int32),
+                ("dir_mode", C.c_int32), ("start_mode", C.c_int32), ("seed", C.c_uint64),
+                ("system", C.c_uint32), ("pad", C.c_uint32)]
+
+
+class Event(C.Structure):
+    _fields_ = [("chain", C.c_int64), ("cell", C.c_int32), ("kind", C.c_int32),
+                ("gid", C.c_int64), ("active", C.c_int64), ("s", C.c_double),
+                ("dx", C.c_double), ("dy", C.c_double), ("ax", C.c_double),
+                ("ay", C.c_double), ("px", C.c_double), ("py", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        src = os.path.join(os.path.dirname(path), "ec_oracle.c")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+            _build.build()
+        L = C.CDLL(path)
+        dp, u64p, i32p, i64p = (C.POINTER(C.c_double), C.POINTER(C.c_uint64),
+                                C.POINTER(C.c_int32), C.POINTER(C.c_int64))
+        pp = C.POINTER(Params)
+        L.orc_box_length.restype = C.c_double
+        L.orc_box_length.argtypes = [C.c_int64, C.c_double, C.c_double]
+        L.orc_philox4x64_10.argtypes = [u64p, u64p, u64p]
+        L.orc_lattice.argtypes = [pp, dp, dp]
+        L.orc_sweep_draws.argtypes = [pp, C.c_int64, dp, dp, i32p]
+        L.orc_start_index.restype = C.c_int64
+        L.orc_start_index.argtypes = [pp, C.c_int64, C.c_int32, C.c_int64, C.c_int64]
+        L.orc_direction.argtypes = [pp, C.c_int64, C.c_int32, C.c_int64, dp, dp]
+        L.orc_collision_distance.restype = C.c_double
+        L.orc_collision_distance.argtypes = [C.c_double] * 5
+        L.orc_assign_cells.restype = C.c_int
+        L.orc_assign_cells.argtypes = [pp, dp, dp, C.c_int64, i32p]
+        L.orc_run.restype = C.c_int
+        L.orc_run.argtypes = [pp, dp, dp, C.c_int64, C.c_int64, dp, u64p, u64p]
+        L.orc_run_cells.restype = C.c_int
+        L.orc_run_cells.argtypes = [pp, dp, dp, C.c_int64, C.c_int32, i32p, C.c_int32, dp, u64p,
+                                    u64p]
+        L.orc_set_log.argtypes = [C.POINTER(Event), C.c_int64]
+        L.orc_log_count.restype = C.c_int64
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def params(n, eta, ell, cells, dir_mode=DIR_ISO, seed=1, sigma=1.0, chains_per_cell=0,
+           start_mode=START_REPLACE, system=0):
+    return Params(int(n), float(sigma), float(eta), float(ell), int(cells), int(chains_per_cell),
+                  int(dir_mode), int(start_mode), int(seed), int(system), 0)
+
+
+def box_length(n, sigma, eta):
+    return lib().orc_box_length(int(n), float(sigma), float(eta))
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(_ptr(c, C.c_uint64), _ptr(k, C.c_uint64), _ptr(out, C.c_uint64))
+    return out
+
+
+def lattice(p):
+    x = np.zeros(p.n, dtype=np.float64)
+    y = np.zeros(p.n, dtype=np.float64)
+    lib().orc_lattice(C.byref(p), _ptr(x, C.c_double), _ptr(y, C.c_double))
+    return x, y
+
+
+def sweep_draws(p, sweep):
+    sx, sy = C.c_double(), C.c_double()
+    perm = np.zeros(4, dtype=np.int32)
+    lib().orc_sweep_draws(C.byref(p), int(sweep), C.byref(sx), C.byref(sy), _ptr(perm, C.c_int32))
+    return sx.value, sy.value, perm
+
+
+def start_index(p, sweep, cell, chain, n_c):
+    return lib().orc_start_index(C.byref(p), int(sweep), int(cell), int(chain), int(n_c))
+
+
+def direction(p, sweep, cell, chain):
+    dx, dy = C.c_double(), C.c_double()
+    lib().orc_direction(C.byref(p), int(sweep), int(cell), int(chain), C.byref(dx), C.byref(dy))
+    return dx.value, dy.value
+
+
+def collision_distance(rx, ry, dx, dy, sigma=1.0):
+    return lib().orc_collision_distance(rx, ry, dx, dy, sigma)
+
+
+def assign_cells(p, x, y, sweep):
+    cell_of = np.zeros(p.n, dtype=np.int32)
+    rc = lib().orc_assign_cells(C.byref(p), _ptr(x, C.c_double), _ptr(y, C.c_double), int(sweep),
+                                _ptr(cell_of, C.c_int32))
+    if rc != 0:
+        raise ValueError("invalid parameters")
+    return cell_of
+
+
+class State:
+    """Positions plus per-cell accumulators, advanced in place by the oracle."""
+
+    def __init__(self, p, x=None, y=None):
+        self.p = p
+        if x is None:
+            x, y = lattice(p)
+        self.x = np.ascontiguousarray(x, dtype=np.float64).copy()
+        self.y = np.ascontiguousarray(y, dtype=np.float64).copy()
+        nc = p.cells * p.cells
+        self.acc_delta = np.zeros(nc, dtype=np.float64)
+        self.acc_cnt = np.zeros((nc, CNT_NCOL), dtype=np.uint64)
+        self.sweep = 0
+        self.digests = []
+
+    def run(self, n_sweeps):
+        d = np.zeros(max(int(n_sweeps), 1), dtype=np.uint64)
+        rc = lib().orc_run(C.byref(self.p), _ptr(self.x, C.c_double), _ptr(self.y, C.c_double),
+                           self.sweep, int(n_sweeps), _ptr(self.acc_delta, C.c_double),
+                           _ptr(self.acc_cnt, C.c_uint64), _ptr(d, C.c_uint64))
+        if rc != 0:
+            raise ValueError("invalid parameters")
+        self.sweep += int(n_sweeps)
+        self.digests.extend(int(v) for v in d[:int(n_sweeps)])
+        return d[:int(n_sweeps)]
+
+    def run_cells(self, sweep, cells, n_phases=1):
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        dig = np.zeros(len(cells), dtype=np.uint64)
+        rc = lib().orc_run_cells(C.byref(self.p), _ptr(self.x, C.c_double),
+                                 _ptr(self.y, C.c_double), int(sweep), int(n_phases),
+                                 _ptr(cells, C.c_int32), len(cells),
+                                 _ptr(self.acc_delta, C.c_double), _ptr(self.acc_cnt, C.c_uint64),
+                                 _ptr(dig, C.c_uint64))
+        if rc != 0:
+            raise ValueError("invalid parameters")
+        return dig
+
+    def tallies(self):
+        """(sum of contact projections, lifts, frozen, walls, chains, pseudo) in cell order."""
+        s = 0.0
+        for v in self.acc_delta:  # fixed cell order
+            s += float(v)
+        cnt = self.acc_cnt.sum(axis=0)
+        return s, [int(v) for v in cnt]
+
+    def pressure(self):
+        """Z = beta P / rho = 1 + sum(contact projections) / (chains * ell)."""
+        s, cnt = self.tallies()
+        chains = cnt[CNT_CHAINS]
+        z = 1.0 + s / (chains * self.p.ell)
+        L = box_length(self.p.n, self.p.sigma, self.p.eta)
+        return z, z * self.p.n * self.p.sigma ** 2 / (L * L)
+
+
+def run_logged(p, x, y, sweep0, n_sweeps, capacity=1 << 20):
+    """Run with the event log on; returns (x, y, events array)."""
+    st = State(p, x, y)
+    st.sweep = sweep0
+    buf = (Event * capacity)()
+    lib().orc_set_log(buf, capacity)
+    try:
+        st.run(n_sweeps)
+        n = lib().orc_log_count()
+    finally:
+        lib().orc_set_log(None, 0)
+    if n > capacity:
+        raise RuntimeError("event log overflow")
+    ev = np.ctypeslib.as_array(buf)[:n].copy()
+    return st, ev

@@ -1,0 +1,483 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: a published
+known-answer (numpy's Philox4x64-10), closed-form geometry, exact small-system
+results, invariants of the event chain, and the hard-disk virial series.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests import inputs
+
+SIG = 1.0
+
+
+# --------------------------------------------------------------------------
+# Random numbers
+# --------------------------------------------------------------------------
+def _numpy_philox_block(ctr, key):
+    """Block for counter `ctr` from numpy's Philox4x64-10, which increments its
+    counter (with carry) before producing a block."""
+    c = [int(v) for v in ctr]
+    # counter one step before ctr, with borrow across words
+    prev = list(c)
+    for i in range(4):
+        if prev[i] > 0:
+            prev[i] -= 1
+            break
+        prev[i] = (1 << 64) - 1
+    g = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(prev, dtype=np.uint64))
+    return [int(v) for v in g.random_raw(4)]
+
+
+@pytest.mark.parametrize("ctr,key", [
+    ([0, 0, 0, 0], [0, 0]),
+    ([1, 0, 0, 0], [1, 2]),
+    ([5, 123, 7, 0], [1, 3]),
+    ([0, 1 << 40, 3, 2], [42, 2]),
+    ([(1 << 64) - 1] * 4, [(1 << 64) - 1] * 2),
+])
+def test_philox_matches_numpy(ctr, key):
+    assert [int(v) for v in O.philox(ctr, key)] == _numpy_philox_block(ctr, key)
+
+
+def test_philox_random_counters_match_numpy():
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        ctr = [int(v) for v in rng.integers(0, 1 << 63, size=4)]
+        key = [int(v) for v in rng.integers(0, 1 << 63, size=2)]
+        assert [int(v) for v in O.philox(ctr, key)] == _numpy_philox_block(ctr, key)
+
+
+def test_start_index_uniform_chi2():
+    """Starts are drawn with replacement, uniformly over the cell's disks."""
+    p = O.params(4096, 0.7, 1.0, 8)
+    n_c = 37
+    counts = np.zeros(n_c)
+    for k in range(n_c * 400):
+        counts[O.start_index(p, 3, 5, k, n_c)] += 1
+    expected = counts.sum() / n_c
+    chi2 = ((counts - expected) ** 2 / expected).sum()
+    # 36 degrees of freedom: P(chi2 > 70) ~ 6e-4
+    assert chi2 < 70.0
+
+
+def test_directions_unit_and_isotropic():
+    p = O.params(4096, 0.7, 1.0, 8)
+    ang = []
+    for k in range(20000):
+        dx, dy = O.direction(p, 1, 2, k)
+        assert abs(math.hypot(dx, dy) - 1.0) < 4e-16
+        ang.append(math.atan2(dy, dx))
+    hist, _ = np.histogram(ang, bins=24, range=(-math.pi, math.pi))
+    e = len(ang) / 24
+    chi2 = ((hist - e) ** 2 / e).sum()
+    assert chi2 < 55.0  # 23 dof, P ~ 2e-4
+
+
+def test_xy_and_x_directions():
+    p = O.params(256, 0.7, 1.0, 1, dir_mode=O.DIR_XY)
+    assert O.direction(p, 0, 0, 0) == (1.0, 0.0)
+    assert O.direction(p, 0, 0, 1) == (0.0, 1.0)
+    p = O.params(256, 0.7, 1.0, 1, dir_mode=O.DIR_X)
+    assert O.direction(p, 0, 0, 1) == (1.0, 0.0)
+
+
+def test_sweep_draws_shift_and_colour_order():
+    p = O.params(65536, 0.7, 20.0, 16)
+    w = O.box_length(p.n, 1.0, 0.7) / 16
+    perms = {}
+    sx_all = []
+    for s in range(2400):
+        sx, sy, perm = O.sweep_draws(p, s)
+        assert 0.0 <= sx <= w and 0.0 <= sy <= w
+        assert sorted(perm.tolist()) == [0, 1, 2, 3]
+        perms[tuple(perm)] = perms.get(tuple(perm), 0) + 1
+        sx_all.append(sx / w)
+    assert len(perms) == 24
+    cnt = np.array(list(perms.values()))
+    chi2 = ((cnt - 100.0) ** 2 / 100.0).sum()
+    assert chi2 < 55.0
+    hist, _ = np.histogram(sx_all, bins=10, range=(0, 1))
+    assert ((hist - 240.0) ** 2 / 240.0).sum() < 30.0
+
+
+# --------------------------------------------------------------------------
+# Geometry
+# --------------------------------------------------------------------------
+def _contact_by_bisection(rx, ry, dx, dy, sigma):
+    """First s >= 0 with |r - s d| = sigma, found by bisection on the distance
+    function (an independent method from the closed form)."""
+    f = lambda s: math.hypot(rx - s * dx, ry - s * dy) - sigma
+    if f(0.0) <= 0.0:
+        a = rx * dx + ry * dy
+        return 0.0 if a > 0 else math.inf
+    # closest approach
+    s_min = rx * dx + ry * dy
+    if s_min <= 0.0 or f(s_min) >= 0.0:
+        return math.inf
+    lo, hi = 0.0, s_min
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid) > 0.0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def test_collision_distance_closed_cases():
+    assert O.collision_distance(3.0, 0.0, 1.0, 0.0) == 2.0           # head-on
+    assert O.collision_distance(-3.0, 0.0, 1.0, 0.0) == math.inf     # behind
+    assert O.collision_distance(3.0, 1.0, 1.0, 0.0) == math.inf      # grazing miss |c| = sigma
+    assert O.collision_distance(3.0, 1.5, 1.0, 0.0) == math.inf      # miss
+    assert O.collision_distance(0.0, 2.0, 0.0, 1.0) == 1.0           # along y
+    assert O.collision_distance(1.0, 0.0, 1.0, 0.0) == 0.0           # touching ahead
+    assert O.collision_distance(0.9, 0.0, 1.0, 0.0) == 0.0           # overlap ahead -> 0
+    assert O.collision_distance(0.0, 1.0, 1.0, 0.0) == math.inf      # touching beside (a = 0)
+    # 3-4-5 triangle: r = (4, 0.6), d = x: s = 4 - sqrt(1 - 0.36) = 3.2
+    assert abs(O.collision_distance(4.0, 0.6, 1.0, 0.0) - 3.2) < 1e-15
+
+
+def test_collision_distance_vs_bisection():
+    rng = np.random.default_rng(3)
+    for _ in range(3000):
+        r = rng.uniform(-4, 4, size=2)
+        if r @ r < 1.0:
+            continue
+        t = rng.uniform(0, 2 * math.pi)
+        d = (math.cos(t), math.sin(t))
+        s1 = O.collision_distance(r[0], r[1], d[0], d[1])
+        s2 = _contact_by_bisection(r[0], r[1], d[0], d[1], SIG)
+        if math.isinf(s2):
+            # the closed form may only disagree on numerically grazing rays
+            c = abs(r[0] * d[1] - r[1] * d[0])
+            assert math.isinf(s1) or c > 1.0 - 1e-9
+        else:
+            assert abs(s1 - s2) < 1e-9 * max(1.0, s2) + 1e-7 * (1.0 if abs(
+                abs(r[0] * d[1] - r[1] * d[0]) - 1.0) < 1e-6 else 0.0)
+
+
+def test_box_length_and_lattice():
+    for n, eta in [(256, 0.70), (65536, 0.70), (1048576, 0.72), (16, 0.05)]:
+        L = O.box_length(n, 1.0, eta)
+        assert abs(n * math.pi / (4 * L * L) - eta) < 1e-14
+        if n <= 65536:
+            p = O.params(n, eta, 1.0, 1)
+            x, y = O.lattice(p)
+            k = int(round(math.sqrt(n)))
+            a = L / k
+            assert x.min() >= 0 and x.max() < L and y.min() >= 0 and y.max() < L
+            if n <= 4096:
+                dxm = x[:, None] - x[None, :]
+                dym = y[:, None] - y[None, :]
+                dxm -= L * np.round(dxm / L)
+                dym -= L * np.round(dym / L)
+                d2 = dxm ** 2 + dym ** 2
+                np.fill_diagonal(d2, np.inf)
+                assert abs(math.sqrt(d2.min()) - a) < 1e-12
+            assert a > 1.0
+
+
+# --------------------------------------------------------------------------
+# Invariants of event chains
+# --------------------------------------------------------------------------
+def _min_pair_distance(x, y, L):
+    dx = x[:, None] - x[None, :]
+    dy = y[:, None] - y[None, :]
+    dx -= L * np.round(dx / L)
+    dy -= L * np.round(dy / L)
+    d2 = dx * dx + dy * dy
+    np.fill_diagonal(d2, np.inf)
+    return math.sqrt(d2.min())
+
+
+def test_periodic_xy_invariants():
+    """Single periodic cell, +x/+y chains: every chain moves the disks by a
+    total of exactly ell along its direction, contacts are at distance sigma,
+    and no two disks ever overlap."""
+    # two chains per sweep (+x then +y) with 2 ell < L/2, so per-disk net
+    # displacements over a sweep are unambiguous under the minimum image
+    p = O.params(256, 0.60, 2.9, 1, dir_mode=O.DIR_XY, seed=11, chains_per_cell=2)
+    L = O.box_length(256, 1.0, 0.60)
+    assert 2 * p.ell < L / 2
+    st = O.State(p)
+    n_lifts = 0
+    for sweep in range(40):
+        xb, yb = st.x.copy(), st.y.copy()
+        st2, ev = O.run_logged(p, xb, yb, sweep, 1)
+        for ch in np.unique(ev["chain"]):
+            e = ev[ev["chain"] == ch]
+            assert abs(e["s"].sum() - p.ell) < 1e-12 * len(e) + 1e-12
+            lifts = e[e["kind"] == O.EV_LIFT]
+            n_lifts += len(lifts)
+            if len(lifts):
+                r = np.hypot((lifts["px"] - lifts["ax"] + L / 2) % L - L / 2,
+                             (lifts["py"] - lifts["ay"] + L / 2) % L - L / 2)
+                assert np.all(np.abs(r - 1.0) < 1e-12)
+            assert e["kind"][-1] == O.EV_END
+        ddx = (st2.x - xb + L / 2) % L - L / 2
+        ddy = (st2.y - yb + L / 2) % L - L / 2
+        assert abs(ddx.sum() - p.ell) < 1e-11
+        assert abs(ddy.sum() - p.ell) < 1e-11
+        assert _min_pair_distance(st2.x, st2.y, L) > 1.0 - 1e-12
+        st.run(1)
+        np.testing.assert_array_equal(st.x, st2.x)
+        np.testing.assert_array_equal(st.y, st2.y)
+    assert n_lifts > 100
+
+
+def test_walled_invariants():
+    """Shifted square cells: disks stay inside their cell during a sweep, every
+    lift and frozen event is a contact at distance sigma, a wall event puts the
+    centre on the wall, one chain per disk per sweep, no overlaps."""
+    n, eta, C = 1024, 0.55, 4
+    p = O.params(n, eta, 6.0, C, seed=5)
+    L = O.box_length(n, 1.0, eta)
+    w = L / C
+    st = O.State(p)
+    for sweep in range(4):
+        x0, y0 = st.x.copy(), st.y.copy()
+        cell_of = O.assign_cells(p, x0, y0, sweep)
+        sx, sy, perm = O.sweep_draws(p, sweep)
+        st2, ev = O.run_logged(p, x0, y0, sweep, 1)
+        assert st2.acc_cnt[:, O.CNT_CHAINS].sum() == n
+        for k in (O.EV_LIFT, O.EV_FROZEN):
+            e = ev[ev["kind"] == k]
+            r = np.hypot(e["px"] - e["ax"], e["py"] - e["ay"])
+            assert np.all(np.abs(r - 1.0) < 1e-12), k
+        ew = ev[ev["kind"] == O.EV_WALL_X]
+        assert np.all(np.minimum(np.abs(ew["ax"]), np.abs(ew["ax"] - w)) < 1e-12)
+        ew = ev[ev["kind"] == O.EV_WALL_Y]
+        assert np.all(np.minimum(np.abs(ew["ay"]), np.abs(ew["ay"] - w)) < 1e-12)
+        assert np.all(ev["ax"] > -1e-12) and np.all(ev["ax"] < w + 1e-12)
+        assert np.all(ev["ay"] > -1e-12) and np.all(ev["ay"] < w + 1e-12)
+        for ch in np.unique(ev["chain"]):
+            e = ev[ev["chain"] == ch]
+            assert abs(e["s"].sum() - p.ell) < 1e-12 * len(e) + 1e-12
+        # every disk is still inside the cell it started the sweep in
+        ux = (st2.x - sx) % L
+        uy = (st2.y - sy) % L
+        cx, cy = cell_of % C, cell_of // C
+        tol = 1e-9
+        inside_x = (ux >= cx * w - tol) & (ux <= (cx + 1) * w + tol) | ((cx == C - 1) & (ux < tol))
+        inside_y = (uy >= cy * w - tol) & (uy <= (cy + 1) * w + tol) | ((cy == C - 1) & (uy < tol))
+        assert inside_x.all() and inside_y.all()
+        assert _min_pair_distance(st2.x, st2.y, L) > 1.0 - 1e-12
+        st.run(1)
+        np.testing.assert_array_equal(st.x, st2.x)
+
+
+def test_frozen_reflection_is_specular():
+    """After a contact with a frozen disk the direction is mirrored about the
+    contact normal: angle of incidence equals angle of reflection."""
+    n, eta, C = 1024, 0.62, 4
+    p = O.params(n, eta, 8.0, C, seed=9)
+    st, ev = O.run_logged(p, None, None, 0, 2)
+    count = 0
+    for i in np.nonzero(ev["kind"] == O.EV_FROZEN)[0]:
+        if i + 1 >= len(ev) or ev["chain"][i + 1] != ev["chain"][i]:
+            continue
+        e, nxt = ev[i], ev[i + 1]
+        nvec = np.array([e["px"] - e["ax"], e["py"] - e["ay"]])
+        nvec /= np.linalg.norm(nvec)
+        d = np.array([e["dx"], e["dy"]])
+        d2 = np.array([nxt["dx"], nxt["dy"]])
+        assert abs(np.linalg.norm(d2) - 1.0) < 1e-14
+        # tangential component kept, normal component reversed
+        t = np.array([-nvec[1], nvec[0]])
+        assert abs(d2 @ t - d @ t) < 1e-12
+        assert abs(d2 @ nvec + d @ nvec) < 1e-12
+        assert d @ nvec > 0  # it was moving towards the frozen disk
+        count += 1
+    assert count > 20
+
+
+def test_single_disk_folds_at_walls():
+    """One disk alone in a walled cell: after a chain its local position is
+    the straight-line end point folded back at the walls."""
+    L = 40.0
+    eta = math.pi / (4.0 * L * L)
+    p = O.params(1, eta, 37.3, 4, seed=21)
+    assert abs(O.box_length(1, 1.0, eta) - L) < 1e-12
+    w = O.box_length(1, 1.0, eta) / 4
+    L = O.box_length(1, 1.0, eta)
+    st = O.State(p, np.array([13.7]), np.array([27.1]))
+
+    def fold(t):
+        u = t % (2 * w)
+        return u if u <= w else 2 * w - u
+
+    for sweep in range(20):
+        x0, y0 = st.x[0], st.y[0]
+        cell = int(O.assign_cells(p, st.x, st.y, sweep)[0])
+        sx, sy, _ = O.sweep_draws(p, sweep)
+        cx, cy = cell % 4, cell // 4
+        vx = (x0 - sx) % L - cx * w
+        vy = (y0 - sy) % L - cy * w
+        dx, dy = O.direction(p, sweep, cell, 0)
+        ex, ey = fold(vx + p.ell * dx), fold(vy + p.ell * dy)
+        st.run(1)
+        gx = (st.x[0] - sx) % L - cx * w
+        gy = (st.y[0] - sy) % L - cy * w
+        assert abs(gx - ex) < 1e-11 and abs(gy - ey) < 1e-11
+
+
+def test_resume_is_bit_exact():
+    p = O.params(1024, 0.65, 5.0, 4, seed=3)
+    a = O.State(p)
+    a.run(6)
+    b = O.State(p)
+    b.run(2)
+    b.run(4)
+    np.testing.assert_array_equal(a.x, b.x)
+    np.testing.assert_array_equal(a.y, b.y)
+    np.testing.assert_array_equal(a.acc_delta, b.acc_delta)
+    assert a.digests == b.digests
+
+
+def test_run_cells_reproduces_first_phase():
+    """First-phase cells only see positions from the start of the sweep, so the
+    single-cell entry reproduces them exactly."""
+    p = O.params(4096, 0.70, 10.0, 8, seed=2)
+    full = O.State(p)
+    full.run(1)
+    _, _, perm = O.sweep_draws(p, 0)
+    C = 8
+    first = [c for c in range(C * C) if ((c % C) & 1) | (((c // C) & 1) << 1) == perm[0]]
+    part = O.State(p)
+    part.run_cells(0, first[:5], n_phases=1)
+    cell_of = O.assign_cells(p, *O.lattice(p), 0)
+    mask = np.isin(cell_of, first[:5])
+    np.testing.assert_array_equal(part.x[mask], full.x[mask])
+    np.testing.assert_array_equal(part.y[mask], full.y[mask])
+    for c in first[:5]:
+        assert part.acc_delta[c] == full.acc_delta[c]
+
+
+# --------------------------------------------------------------------------
+# Statistical pins: exact small systems and the virial series
+# --------------------------------------------------------------------------
+def _batch_mean_err(vals, nb=20):
+    vals = np.asarray(vals)
+    m = len(vals) // nb
+    b = vals[: m * nb].reshape(nb, m).mean(axis=1)
+    return b.mean(), b.std(ddof=1) / math.sqrt(nb)
+
+
+def _two_disk_cdf(r, L, s=1.0):
+    """CDF of the separation of two disks uniform on an L x L torus, excluded
+    core of radius s, for s <= r <= L/sqrt(2)."""
+    def area(r):
+        if r <= L / 2:
+            return math.pi * r * r
+        h = L / 2
+        return math.pi * r * r - 4 * (r * r * math.acos(h / r) - h * math.sqrt(r * r - h * h))
+    return (area(r) - math.pi * s * s) / (L * L - math.pi * s * s)
+
+
+def test_two_disks_periodic_exact():
+    """Two disks in a periodic L x L box, L = 4 sigma: the separation is
+    uniform over the torus minus the excluded disk and the EC pressure is
+    Z = 1 + pi sigma^2 / (2 (L^2 - pi sigma^2))."""
+    L = 4.0
+    eta = 2 * math.pi / (4 * L * L)
+    p = O.params(2, eta, 3.0, 1, dir_mode=O.DIR_ISO, seed=17)
+    st = O.State(p, np.array([0.5, 2.5]), np.array([0.5, 0.5]))
+    seps = []
+    zs = []
+    prev_delta, prev_chains = 0.0, 0
+    for _ in range(400):
+        st.run(500)
+        d = np.array([st.x[1] - st.x[0], st.y[1] - st.y[0]])
+        d -= L * np.round(d / L)
+        seps.append(float(np.hypot(*d)))
+        s, cnt = st.tallies()
+        zs.append((s - prev_delta) / ((cnt[O.CNT_CHAINS] - prev_chains) * p.ell))
+        prev_delta, prev_chains = s, cnt[O.CNT_CHAINS]
+    z_exact = 1.0 + math.pi / (2 * (L * L - math.pi))
+    m, e = _batch_mean_err(zs)
+    assert abs(1.0 + m - z_exact) < 4 * e + 1e-3, (1 + m, z_exact, e)
+    assert e < 0.01
+    assert st.acc_cnt[0, O.CNT_PSEUDO] > 0
+    # KS test of the separation distribution
+    seps = np.sort(seps)
+    F = np.array([_two_disk_cdf(r, L) for r in seps])
+    emp = np.arange(1, len(seps) + 1) / len(seps)
+    ks = max(np.abs(F - emp).max(), np.abs(F - (emp - 1.0 / len(seps))).max())
+    assert ks < 1.63 / math.sqrt(len(seps)) * 1.2  # ~1% level
+
+
+def test_tonks_gas_pressure():
+    """Hard rods on a ring (disks on one row, +x chains only).  For N rods of
+    length sigma on a ring of length L the free gaps are uniform on the
+    simplex, each gap is (L - N sigma) Beta(1, N-1), and the contact density
+    gives Z = 1 + (N-1) sigma / (L - N sigma) (-> 1/(1 - N sigma/L) for large N).
+    The start has random gaps: from equal gaps and an integer ell the +x
+    dynamics would stay on a lattice of gap values."""
+    n = 16
+    L = 32.0
+    eta = n * math.pi / (4 * L * L)
+    p = O.params(n, eta, 10.0, 1, dir_mode=O.DIR_X, seed=23)
+    x, y = inputs.rods_on_a_ring(n, L, seed=5)
+    st = O.State(p, x, y)
+    st.run(200)
+    st.acc_delta[:] = 0
+    st.acc_cnt[:] = 0
+    zs = []
+    prev = (0.0, 0)
+    gaps = []
+    for _ in range(400):
+        st.run(25)
+        s, cnt = st.tallies()
+        zs.append((s - prev[0]) / ((cnt[O.CNT_CHAINS] - prev[1]) * p.ell))
+        prev = (s, cnt[O.CNT_CHAINS])
+        ahead = (st.x - st.x[0]) % L  # gap in front of rod 0
+        ahead[0] = np.inf
+        gaps.append(ahead.min() - 1.0)
+    assert np.all(st.y == y[0])
+    m, e = _batch_mean_err(zs)
+    z_exact = 1.0 + (n - 1) / (L - n)
+    assert abs(1.0 + m - z_exact) < 4 * e + 1e-3, (1 + m, z_exact, e)
+    # KS test of the gap in front of one rod against (L - N sigma) Beta(1, N-1)
+    gaps = np.sort(np.array(gaps))
+    F = 1.0 - (1.0 - gaps / (L - n)) ** (n - 1)
+    emp = np.arange(1, len(gaps) + 1) / len(gaps)
+    ks = max(np.abs(F - emp).max(), np.abs(F - (emp - 1.0 / len(gaps))).max())
+    assert ks < 1.63 / math.sqrt(len(gaps))
+
+
+@pytest.mark.parametrize("cells", [1, 4])
+def test_low_density_virial_series(cells):
+    """At eta = 0.08 the EC pressure matches the hard-disk virial series
+    Z = 1 + 2 eta + 3.12802 eta^2 + 4.25785 eta^3 + 5.3369 eta^4 (the
+    coefficients are B3/B2^2 = 4/3 - sqrt(3)/pi and
+    B4/B2^3 = 2 - 9 sqrt(3)/(2 pi) + 10/pi^2 in units of 2 eta), both in one
+    periodic cell and with walled cells and frozen neighbours."""
+    eta = 0.08
+    n, per = (256, 20) if cells == 1 else (1024, 10)
+    b3 = 4.0 * (4.0 / 3.0 - math.sqrt(3.0) / math.pi)
+    b4 = 8.0 * (2.0 - 9.0 * math.sqrt(3.0) / (2.0 * math.pi) + 10.0 / math.pi ** 2)
+    z_series = 1 + 2 * eta + b3 * eta ** 2 + b4 * eta ** 3 + 5.3369 * eta ** 4
+    z_series -= 2 * eta / n  # finite-N second virial correction
+    p = O.params(n, eta, 30.0, cells, dir_mode=O.DIR_ISO, seed=31)
+    st = O.State(p)
+    st.run(20)  # melt the lattice
+    st.acc_delta[:] = 0
+    st.acc_cnt[:] = 0
+    zs = []
+    prev = (0.0, 0)
+    for _ in range(40):
+        st.run(per)
+        s, cnt = st.tallies()
+        zs.append(1.0 + (s - prev[0]) / ((cnt[O.CNT_CHAINS] - prev[1]) * p.ell))
+        prev = (s, cnt[O.CNT_CHAINS])
+    m, e = _batch_mean_err(zs)
+    # the eta^5 term (~2e-5) and O(eta^2/N) corrections are below the tolerance
+    assert abs(m - z_series) < 4 * e + 3e-4, (m, z_series, e)
+    assert e < 3e-4
+    if cells > 1:
+        assert st.acc_cnt[:, O.CNT_FROZEN].sum() > 0.02 * st.acc_cnt[:, O.CNT_LIFTS].sum()
