@@ -1,0 +1,177 @@
+/*
+ * ec.h -- C ABI of the MI355X (gfx950) parallel event-chain library for
+ * two-dimensional hard disks.
+ *
+ * The method (Kampmann, Boltz, Kierfeld, "Parallelized event chain algorithm
+ * for dense hard sphere and polymer systems"):
+ *   - N hard disks of diameter sigma in a periodic L x L box, packing fraction
+ *     eta = N pi sigma^2 / (4 L^2)                                  (Sec. 2);
+ *   - straight event chains: a disk moves along d until it touches another,
+ *     the remaining displacement passes to the hit disk, until a total of ell
+ *     is used up                                                    (Sec. 3.2);
+ *   - parallel sweep: the box is cut into C x C square simulation cells
+ *     shifted by a random vector, grouped in 2 x 2 blocks; one random order
+ *     of the four colours per sweep; in each cell n_m start disks are drawn
+ *     WITH replacement and one chain is run from each while all other cells
+ *     are frozen; chains reflect at cell walls and at frozen disks with equal
+ *     angles of incidence and reflection                          (Sec. 3.4,
+ *     Fig. 1, Fig. 2).
+ *
+ * Every call returns ec_status (EC_OK = 0).  No exception crosses the ABI.
+ *
+ * Memory: the caller allocates one device buffer of ec_workspace_bytes()
+ * bytes (for instance a torch uint8 tensor) and keeps it alive until
+ * ec_destroy.  The library allocates no device memory.  The host handle is
+ * created by ec_init_system and freed by ec_destroy.  Host arrays passed to
+ * the get/set calls belong to the caller.
+ *
+ * Streams: every device operation is enqueued on the stream given at init
+ * (a hipStream_t passed as void*, NULL = the null stream), in call order.
+ * Calls that return host data synchronise that stream.
+ *
+ * Threading: a handle may be used by one host thread at a time.
+ *
+ * Determinism: results are a pure function of the parameters, the seed and
+ * the number of sweeps done; sweeps may be split over any number of calls.
+ * Given the same inputs the device path reproduces the CPU reference bit for
+ * bit (same event sequence, same positions).
+ */
+#ifndef EC_H
+#define EC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EC_ABI_VERSION 1u
+
+typedef enum {
+  EC_OK = 0,
+  EC_E_INVALID = 1,     /* invalid argument; nothing was changed            */
+  EC_E_OVERLAP = 2,     /* positions given with two disks closer than sigma  */
+  EC_E_HIP = 3,         /* a HIP runtime call failed (see ec_last_error)     */
+  EC_E_NOMEM = 4,       /* workspace too small                               */
+  EC_E_STATE = 5,       /* a device-side capacity check failed in a sweep    */
+  EC_E_UNSUPPORTED = 6  /* valid request this build does not implement       */
+} ec_status;
+
+typedef enum {
+  EC_DIR_XY = 0,        /* +x for even chains, +y for odd ones; one periodic cell only (Sec. 3.2) */
+  EC_DIR_ISOTROPIC = 1, /* uniform direction on the circle (required with C > 1)                 */
+  EC_DIR_X = 2          /* +x only; one periodic cell only                                       */
+} ec_dir_mode;
+
+typedef enum {
+  EC_PREC_FP64 = 0,        /* every candidate distance in FP64                               */
+  EC_PREC_FP32_SCREEN = 1  /* FP32 screening with a guard band, FP64 for the survivors,
+                              the winner and every commit; identical events to EC_PREC_FP64 */
+} ec_precision;
+
+typedef enum {
+  EC_START_REPLACE = 0,  /* starts drawn with replacement: the correct rule (Sec. 3.4, Fig. 2) */
+  EC_START_DISTINCT = 1  /* shuffled list of distinct disks: the rule shown to be incorrect
+                            for n_m > 1 (Fig. 3); a negative control only                   */
+} ec_start_mode;
+
+/* ec_params.flags */
+#define EC_FLAG_SCAN_SEARCH 1u  /* walled cells: search every staged disk for each event
+                                   instead of the 4x4-bin window (same events, slower)     */
+
+typedef struct {
+  uint32_t abi_version;     /* must equal EC_ABI_VERSION                                    */
+  uint32_t flags;           /* EC_FLAG_* bits, 0 = default                                  */
+  int64_t  n_disks;         /* N; the lattice start needs N = k*k with k even               */
+  double   sigma;           /* disk diameter, > 0                                           */
+  double   eta;             /* 0 < eta < pi/(2 sqrt 3); L = sigma sqrt(N pi / (4 eta))       */
+  double   ell;             /* displacement of one chain, > 0                               */
+  int32_t  cells_per_side;  /* C: 1 = one periodic cell without walls; else even, >= 4,
+                               and cell side L/C > sigma                                    */
+  int32_t  chains_per_cell; /* <= 0: n_m = number of disks in the cell; > 0: fixed n_m      */
+  int32_t  dir_mode;        /* ec_dir_mode                                                  */
+  int32_t  precision;       /* ec_precision                                                 */
+  int32_t  start_mode;      /* ec_start_mode                                                */
+  int32_t  cells_per_block; /* schedule only: simulation cells per workgroup, 0 = default   */
+  double   screen_margin;   /* relative guard band of EC_PREC_FP32_SCREEN, 0 = 1e-5         */
+  uint64_t seed;            /* Philox4x64-10 key word                                       */
+  uint32_t system;          /* index of the system inside a batch (second key-word part)    */
+  uint32_t reserved;
+} ec_params;
+
+typedef struct ec_system_s* ec_system;
+
+/* Bytes of device workspace a system with these parameters needs.
+ * EC_E_INVALID for invalid parameters (see ec_init_system). */
+ec_status ec_workspace_bytes(const ec_params* p, size_t* bytes);
+
+/* Create a system: validates p, lays out the workspace, places the disks on
+ * the k x k start lattice (odd rows shifted by half a spacing) and clears the
+ * tallies.  dev_workspace: device pointer, ws_bytes >= ec_workspace_bytes().
+ * hip_stream: hipStream_t (borrowed; NULL = null stream).
+ * Errors: EC_E_INVALID (bad parameters, including N not an even square),
+ * EC_E_NOMEM (workspace too small), EC_E_HIP. */
+ec_status ec_init_system(const ec_params* p, void* dev_workspace, size_t ws_bytes,
+                         void* hip_stream, ec_system* out);
+
+/* Enqueue n_sweeps PEC sweeps (Sec. 3.4 steps 1-7; with C = 1, N chains in
+ * the one periodic box).  Asynchronous; advances the sweep counter. */
+ec_status ec_sweep(ec_system sys, int64_t n_sweeps);
+
+/* EC pressure over the sweeps since the last reset (the collision-statistics
+ * route cited in Sec. 3.4, extended to frozen-disk contacts):
+ *   z = beta P / rho = 1 + sum(contact projections) / (n_chains * ell),
+ *   beta_p_sigma2 = z * N sigma^2 / L^2.
+ * counts (may be NULL) receives 5 uint64: lifts, frozen-disk reflections,
+ * wall reflections, chains, periodic free-flight caps.  Synchronises.
+ * EC_E_STATE if a device check failed since init (cell or bin capacity, events
+ * per chain, draw retries; ec_last_error names the first tripped chain). */
+ec_status ec_measure_pressure(ec_system sys, double* z, double* beta_p_sigma2, uint64_t* counts);
+
+/* Clear the pressure tallies (asynchronous). */
+ec_status ec_reset_tallies(ec_system sys);
+
+/* Copy positions to host arrays x[n], y[n] in disk-id order, coordinates in
+ * [0, L).  n must equal N.  Synchronises. */
+ec_status ec_get_positions(ec_system sys, double* x, double* y, int64_t n);
+
+/* Replace all positions (host arrays in disk-id order, any real values; they
+ * are wrapped into [0, L)).  EC_E_OVERLAP, with nothing changed, if two disks
+ * are closer than sigma (periodic minimum image).  Synchronises. */
+ec_status ec_set_positions(ec_system sys, const double* x, const double* y, int64_t n);
+
+/* Event digests of the last n sweeps (oldest first; n <= min(sweeps done,
+ * 1024)).  Synchronises. */
+ec_status ec_get_digests(ec_system sys, uint64_t* out, int64_t n);
+
+/* Per-cell accumulators in cell order (cell = cy*C + cx): delta[C*C] sums of
+ * contact projections, counts[C*C*5] as in ec_measure_pressure.  Synchronises. */
+ec_status ec_get_cell_tallies(ec_system sys, double* delta, uint64_t* counts);
+
+/* Event digest of every cell (cell order) for the last sweep in which that
+ * cell ran; the sweep digest is sum_c digest_c * (2c + 1) mod 2^64.
+ * out[C*C].  Synchronises. */
+ec_status ec_get_cell_digests(ec_system sys, uint64_t* out);
+
+/* Sweeps done so far. */
+ec_status ec_get_sweep_count(ec_system sys, int64_t* sweeps);
+
+/* Timing of the simulation-cell kernels: with on != 0, every later ec_sweep
+ * records HIP events around each colour-phase launch on the system's stream,
+ * synchronises after each sweep and adds the phase durations up.  Switching
+ * on or off clears the totals.  Off by default (sweeps stay asynchronous). */
+ec_status ec_set_timing(ec_system sys, int32_t on);
+/* Summed phase-kernel milliseconds and number of phase launches timed. */
+ec_status ec_get_timing(ec_system sys, double* phase_ms, int64_t* launches);
+
+/* Destroy the handle (does not free the caller's workspace).  Synchronises. */
+ec_status ec_destroy(ec_system sys);
+
+const char* ec_status_string(ec_status s);
+/* Text of the last error on this handle ("" if none); valid until the next call. */
+const char* ec_last_error(ec_system sys);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

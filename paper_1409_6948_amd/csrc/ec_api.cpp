@@ -1,0 +1,463 @@
+// C ABI of the gfx950 parallel event-chain library (declared in include/ec.h):
+// parameter checks, workspace layout, launch order, host/device copies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ec.h"
+#include "ec_internal.h"
+
+namespace {
+
+// pi rounded to the nearest double
+constexpr double kPi = 3.14159265358979323846;
+
+struct Layout {
+  size_t x, y, cell_of, cell_ids, cell_count, cell_fill, cell_start, acc_delta, acc_cnt, ring, cell_digest,
+      draws, err, red, chain_start, chain_dir, shuffle, dbg, total;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell) {
+  Layout l;
+  size_t o = 0;
+  size_t nc = (size_t)C * (size_t)C;
+  size_t max_chains = chains_per_cell > 0 ? nc * (size_t)chains_per_cell : (size_t)n;
+  if (C == 1) max_chains = 0;  // the periodic kernel draws its chains itself
+  l.x = o;          o = align256(o + 8 * (size_t)n);
+  l.y = o;          o = align256(o + 8 * (size_t)n);
+  l.cell_of = o;    o = align256(o + 4 * (size_t)n);
+  l.cell_ids = o;   o = align256(o + 4 * (size_t)n);
+  l.cell_count = o; o = align256(o + 4 * nc);
+  l.cell_fill = o;  o = align256(o + 4 * nc);
+  l.cell_start = o; o = align256(o + 4 * (nc + 1));
+  l.acc_delta = o;  o = align256(o + 8 * nc);
+  l.acc_cnt = o;    o = align256(o + 8 * ec::CNT_NCOL * nc);
+  l.ring = o;       o = align256(o + 8 * (size_t)ec::kDigestRing);
+  l.cell_digest = o; o = align256(o + 8 * nc);
+  l.draws = o;      o = align256(o + sizeof(ec::SweepDraws));
+  l.err = o;        o = align256(o + 8);
+  l.red = o;        o = align256(o + 64);
+  l.chain_start = o; o = align256(o + 4 * max_chains);
+  l.chain_dir = o;  o = align256(o + 16 * max_chains);
+  l.shuffle = o;    o = align256(o + (C == 1 ? 0 : 4 * (size_t)n));
+  l.dbg = o;        o = align256(o + 8 * ec::kDebugWords);
+  l.total = o;
+  return l;
+}
+
+struct Derived {
+  double L, w;
+  int32_t nb, cap_own, cpb, lds_per_cell;
+};
+
+// Oler's bound: at most (2/sqrt 3) A/s^2 + P/(2s) + 1 points with mutual
+// distance >= s fit in a convex region of area A and perimeter P.
+int32_t own_capacity(double w, double sigma) {
+  double u = w / sigma + 1e-6;
+  double bound = (2.0 / std::sqrt(3.0)) * u * u + 2.0 * u + 1.0;
+  int32_t cap = (int32_t)std::ceil(bound);
+  return (cap + 63) & ~63;
+}
+
+ec_status validate(const ec_params* p, Derived* out, std::string* why) {
+  if (!p) { *why = "null parameters"; return EC_E_INVALID; }
+  if (p->abi_version != EC_ABI_VERSION) { *why = "abi_version mismatch"; return EC_E_INVALID; }
+  if (p->n_disks < 1 || p->n_disks > 0x7FFFFFF0LL) { *why = "n_disks out of range"; return EC_E_INVALID; }
+  if (!(p->sigma > 0.0) || !std::isfinite(p->sigma)) { *why = "sigma must be > 0"; return EC_E_INVALID; }
+  if (!(p->eta > 0.0) || !(p->eta < kPi / (2.0 * std::sqrt(3.0)))) {
+    *why = "eta must lie in (0, pi/(2 sqrt 3))"; return EC_E_INVALID;
+  }
+  if (!(p->ell > 0.0) || !std::isfinite(p->ell)) { *why = "ell must be > 0"; return EC_E_INVALID; }
+  if (p->dir_mode < 0 || p->dir_mode > 2) { *why = "bad dir_mode"; return EC_E_INVALID; }
+  if (p->start_mode < 0 || p->start_mode > 1) { *why = "bad start_mode"; return EC_E_INVALID; }
+  if (p->precision < 0 || p->precision > 1) { *why = "bad precision"; return EC_E_INVALID; }
+  const int32_t C = p->cells_per_side;
+  double L = p->sigma * std::sqrt((double)p->n_disks * kPi / (4.0 * p->eta));
+  out->L = L;
+  if (C == 1) {
+    if (!(L > 2.0 * p->sigma)) { *why = "one periodic cell needs L > 2 sigma"; return EC_E_INVALID; }
+    if (p->n_disks > ec::kPeriodicMaxN) {
+      *why = "one periodic cell supports at most 2048 disks"; return EC_E_UNSUPPORTED;
+    }
+    out->w = L; out->nb = 0; out->cap_own = 0; out->cpb = 1; out->lds_per_cell = 0;
+  } else {
+    if (C < 4 || (C & 1)) { *why = "cells_per_side must be 1 or even and >= 4"; return EC_E_INVALID; }
+    if (p->dir_mode != EC_DIR_ISOTROPIC) {
+      *why = "walled cells need isotropic directions"; return EC_E_INVALID;
+    }
+    double w = L / (double)C;
+    if (!(w > p->sigma)) { *why = "cell side must exceed sigma"; return EC_E_INVALID; }
+    int32_t nb = (int32_t)std::floor(w / p->sigma);
+    if (nb < 3) { *why = "cell side below 3 sigma is not supported"; return EC_E_UNSUPPORTED; }
+    out->w = w;
+    out->nb = nb;
+    out->cap_own = own_capacity(w, p->sigma);
+    int32_t cpb = p->cells_per_block == 0 ? 1 : p->cells_per_block;
+    if (cpb != 1 && cpb != 2 && cpb != 4) { *why = "cells_per_block must be 0, 1, 2 or 4"; return EC_E_INVALID; }
+    out->cpb = cpb;
+    out->lds_per_cell = ec::cell_lds_layout(nb + 2, out->cap_own).bytes;
+    if ((size_t)cpb * out->lds_per_cell > 160 * 1024) {
+      *why = "LDS per workgroup exceeds 160 KiB"; return EC_E_UNSUPPORTED;
+    }
+  }
+  if (p->precision == EC_PREC_FP32_SCREEN) {
+    *why = "FP32 screening is not built yet"; return EC_E_UNSUPPORTED;
+  }
+  // lattice start: k = ceil(sqrt(N)) columns, spacing L/k must exceed sigma
+  int64_t k = (int64_t)std::ceil(std::sqrt((double)p->n_disks));
+  while (k * k < p->n_disks) ++k;
+  if (!(L / (double)k > p->sigma)) { *why = "start lattice spacing below sigma"; return EC_E_INVALID; }
+  return EC_OK;
+}
+
+}  // namespace
+
+struct ec_system_s {
+  ec_params p;
+  Derived dv;
+  Layout lay;
+  ec::Dev dev;
+  hipStream_t stream;
+  int64_t sweeps;
+  std::string last_error;
+  // optional phase-kernel timing
+  bool timing;
+  ec::PhaseEvents ev;
+  double phase_ms;
+  int64_t phase_launches;
+};
+
+namespace {
+
+ec_status hip_fail(ec_system s, hipError_t e, const char* what) {
+  if (s) {
+    s->last_error = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return EC_E_HIP;
+}
+
+#define EC_HIP(sys, call)                                  \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return hip_fail(sys, e_, #call); \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* ec_status_string(ec_status s) {
+  switch (s) {
+    case EC_OK: return "ok";
+    case EC_E_INVALID: return "invalid argument";
+    case EC_E_OVERLAP: return "overlapping disks";
+    case EC_E_HIP: return "HIP runtime error";
+    case EC_E_NOMEM: return "workspace too small";
+    case EC_E_STATE: return "device capacity check failed";
+    case EC_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* ec_last_error(ec_system sys) { return sys ? sys->last_error.c_str() : ""; }
+
+ec_status ec_workspace_bytes(const ec_params* p, size_t* bytes) {
+  Derived dv;
+  std::string why;
+  ec_status st = validate(p, &dv, &why);
+  if (st != EC_OK) return st;
+  if (!bytes) return EC_E_INVALID;
+  *bytes = make_layout(p->n_disks, p->cells_per_side, p->chains_per_cell).total;
+  return EC_OK;
+}
+
+ec_status ec_init_system(const ec_params* p, void* ws, size_t ws_bytes, void* stream,
+                         ec_system* out) {
+  if (!out || !ws) return EC_E_INVALID;
+  *out = nullptr;
+  Derived dv;
+  std::string why;
+  ec_status st = validate(p, &dv, &why);
+  if (st != EC_OK) return st;
+  Layout lay = make_layout(p->n_disks, p->cells_per_side, p->chains_per_cell);
+  if (ws_bytes < lay.total) return EC_E_NOMEM;
+  ec_system s = new (std::nothrow) ec_system_s();
+  if (!s) return EC_E_NOMEM;
+  s->p = *p;
+  s->dv = dv;
+  s->lay = lay;
+  s->stream = (hipStream_t)stream;
+  s->sweeps = 0;
+  s->timing = false;
+  s->phase_ms = 0.0;
+  s->phase_launches = 0;
+  unsigned char* b = (unsigned char*)ws;
+  ec::Dev& d = s->dev;
+  d.x = (double*)(b + lay.x);
+  d.y = (double*)(b + lay.y);
+  d.cell_of = (int32_t*)(b + lay.cell_of);
+  d.cell_ids = (int32_t*)(b + lay.cell_ids);
+  d.cell_count = (int32_t*)(b + lay.cell_count);
+  d.cell_fill = (int32_t*)(b + lay.cell_fill);
+  d.cell_start = (int32_t*)(b + lay.cell_start);
+  d.acc_delta = (double*)(b + lay.acc_delta);
+  d.acc_cnt = (unsigned long long*)(b + lay.acc_cnt);
+  d.digest_ring = (unsigned long long*)(b + lay.ring);
+  d.cell_digest = (unsigned long long*)(b + lay.cell_digest);
+  d.draws = (ec::SweepDraws*)(b + lay.draws);
+  d.err = (int32_t*)(b + lay.err);
+  d.red = (double*)(b + lay.red);
+  d.chain_start = (int32_t*)(b + lay.chain_start);
+  d.chain_dir = (double2*)(b + lay.chain_dir);
+  d.shuffle = (int32_t*)(b + lay.shuffle);
+  d.dbg = (double*)(b + lay.dbg);
+  d.search = (p->flags & EC_FLAG_SCAN_SEARCH) ? 1 : 0;
+  d.n = p->n_disks;
+  d.sigma = p->sigma;
+  d.sig2 = p->sigma * p->sigma;
+  d.ell = p->ell;
+  d.L = dv.L;
+  d.half_L = 0.5 * dv.L;
+  d.w = dv.w;
+  d.cap = 0.5 * dv.L - p->sigma;
+  d.C = p->cells_per_side;
+  d.nb = dv.nb;
+  d.gridb = dv.nb + 2;
+  d.b = dv.nb > 0 ? dv.w / (double)dv.nb : 0.0;
+  d.inv_b = dv.nb > 0 ? 1.0 / d.b : 0.0;
+  d.margin = p->screen_margin > 0.0 ? p->screen_margin : 1e-5;
+  d.cap_own = dv.cap_own;
+  d.chains_per_cell = p->chains_per_cell;
+  d.dir_mode = p->dir_mode;
+  d.start_mode = p->start_mode;
+  d.precision = p->precision;
+  d.lds_per_cell = dv.lds_per_cell;
+  d.cells_per_block = dv.cpb;
+  d.seed = p->seed;
+  d.system = p->system;
+
+  int64_t k = (int64_t)std::ceil(std::sqrt((double)p->n_disks));
+  while (k * k < p->n_disks) ++k;
+  double a = dv.L / (double)k;
+  hipError_t e = ec::launch_lattice(d, k, a, s->stream);
+  if (e == hipSuccess) e = ec::launch_zero_tallies(d, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.err, 0, 8, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.dbg, 0, 8 * ec::kDebugWords, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.digest_ring, 0, 8 * ec::kDigestRing, s->stream);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(d.cell_digest, 0, 8 * (size_t)d.C * (size_t)d.C, s->stream);
+  if (e != hipSuccess) {
+    ec_status r = hip_fail(s, e, "init");
+    delete s;
+    return r;
+  }
+  *out = s;
+  return EC_OK;
+}
+
+ec_status ec_sweep(ec_system s, int64_t n_sweeps) {
+  if (!s || n_sweeps < 0) return EC_E_INVALID;
+  for (int64_t i = 0; i < n_sweeps; ++i) {
+    if (s->timing) {
+      EC_HIP(s, ec::launch_sweep(s->dev, s->sweeps, s->stream, &s->ev));
+      EC_HIP(s, hipStreamSynchronize(s->stream));
+      int nq = s->p.cells_per_side == 1 ? 1 : 4;
+      for (int q = 0; q < nq; ++q) {
+        float ms = 0.f;
+        EC_HIP(s, hipEventElapsedTime(&ms, s->ev.begin[q], s->ev.end[q]));
+        s->phase_ms += ms;
+        s->phase_launches += 1;
+      }
+    } else {
+      EC_HIP(s, ec::launch_sweep(s->dev, s->sweeps, s->stream));
+    }
+    s->sweeps += 1;
+  }
+  return EC_OK;
+}
+
+ec_status ec_set_timing(ec_system s, int32_t on) {
+  if (!s) return EC_E_INVALID;
+  if (on && !s->timing) {
+    for (int q = 0; q < 4; ++q) {
+      EC_HIP(s, hipEventCreate(&s->ev.begin[q]));
+      EC_HIP(s, hipEventCreate(&s->ev.end[q]));
+    }
+    s->timing = true;
+  }
+  if (!on && s->timing) {
+    EC_HIP(s, hipStreamSynchronize(s->stream));
+    for (int q = 0; q < 4; ++q) {
+      hipEventDestroy(s->ev.begin[q]);
+      hipEventDestroy(s->ev.end[q]);
+    }
+    s->timing = false;
+  }
+  s->phase_ms = 0.0;
+  s->phase_launches = 0;
+  return EC_OK;
+}
+
+ec_status ec_get_timing(ec_system s, double* phase_ms, int64_t* launches) {
+  if (!s || !phase_ms || !launches) return EC_E_INVALID;
+  *phase_ms = s->phase_ms;
+  *launches = s->phase_launches;
+  return EC_OK;
+}
+
+static ec_status check_err(ec_system s) {
+  int32_t err[2] = {0, 0};
+  double dbg[ec::kDebugWords];
+  EC_HIP(s, hipMemcpyAsync(err, s->dev.err, 8, hipMemcpyDeviceToHost, s->stream));
+  EC_HIP(s, hipMemcpyAsync(dbg, s->dev.dbg, sizeof dbg, hipMemcpyDeviceToHost, s->stream));
+  EC_HIP(s, hipStreamSynchronize(s->stream));
+  if (err[0] != 0) {
+    char buf[512];
+    std::snprintf(buf, sizeof buf,
+                  "device check failed (bits 0x%x: 1 cell capacity, 2 bin capacity, 4 events per "
+                  "chain, 8 draw retries); first tripped chain: cell %.0f chain %.0f sweep %.0f "
+                  "phase %.0f pos (%.17g, %.17g) dir (%.17g, %.17g) rem %.17g slot %.0f id %.0f "
+                  "n_own %.0f",
+                  err[0], dbg[0], dbg[1], dbg[2], dbg[3], dbg[4], dbg[5], dbg[6], dbg[7], dbg[8],
+                  dbg[9], dbg[10], dbg[11]);
+    s->last_error = buf;
+    return EC_E_STATE;
+  }
+  return EC_OK;
+}
+
+ec_status ec_measure_pressure(ec_system s, double* z, double* bp, uint64_t* counts) {
+  if (!s) return EC_E_INVALID;
+  EC_HIP(s, ec::launch_reduce(s->dev, s->stream));
+  double red[8];
+  EC_HIP(s, hipMemcpyAsync(red, s->dev.red, sizeof red, hipMemcpyDeviceToHost, s->stream));
+  ec_status st = check_err(s);
+  if (st != EC_OK) return st;
+  uint64_t cnt[ec::CNT_NCOL];
+  for (int k = 0; k < ec::CNT_NCOL; ++k) std::memcpy(&cnt[k], &red[1 + k], 8);
+  double chains = (double)cnt[ec::CNT_CHAINS];
+  double zz = chains > 0 ? 1.0 + red[0] / (chains * s->p.ell) : 1.0;
+  if (z) *z = zz;
+  if (bp) *bp = zz * (double)s->p.n_disks * s->p.sigma * s->p.sigma / (s->dv.L * s->dv.L);
+  if (counts) for (int k = 0; k < ec::CNT_NCOL; ++k) counts[k] = cnt[k];
+  return EC_OK;
+}
+
+ec_status ec_reset_tallies(ec_system s) {
+  if (!s) return EC_E_INVALID;
+  EC_HIP(s, ec::launch_zero_tallies(s->dev, s->stream));
+  return EC_OK;
+}
+
+ec_status ec_get_positions(ec_system s, double* x, double* y, int64_t n) {
+  if (!s || !x || !y || n != s->p.n_disks) return EC_E_INVALID;
+  EC_HIP(s, hipMemcpyAsync(x, s->dev.x, 8 * (size_t)n, hipMemcpyDeviceToHost, s->stream));
+  EC_HIP(s, hipMemcpyAsync(y, s->dev.y, 8 * (size_t)n, hipMemcpyDeviceToHost, s->stream));
+  return check_err(s);
+}
+
+ec_status ec_set_positions(ec_system s, const double* x, const double* y, int64_t n) {
+  if (!s || !x || !y || n != s->p.n_disks) return EC_E_INVALID;
+  const double L = s->dv.L, sigma = s->p.sigma;
+  std::vector<double> hx((size_t)n), hy((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(x[i]) || !std::isfinite(y[i])) return EC_E_INVALID;
+    double vx = std::fmod(x[i], L), vy = std::fmod(y[i], L);
+    if (vx < 0.0) vx += L;
+    if (vy < 0.0) vy += L;
+    if (vx >= L) vx -= L;
+    if (vy >= L) vy -= L;
+    hx[(size_t)i] = vx;
+    hy[(size_t)i] = vy;
+  }
+  // overlap check with a grid of side >= sigma (minimum image)
+  int64_t g = (int64_t)std::floor(L / sigma);
+  if (g < 1) g = 1;
+  if (g > 4096) g = 4096;
+  double gs = L / (double)g;
+  std::vector<int64_t> head((size_t)(g * g), -1), next((size_t)n, -1);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t cx = std::min<int64_t>((int64_t)(hx[(size_t)i] / gs), g - 1);
+    int64_t cy = std::min<int64_t>((int64_t)(hy[(size_t)i] / gs), g - 1);
+    next[(size_t)i] = head[(size_t)(cy * g + cx)];
+    head[(size_t)(cy * g + cx)] = i;
+  }
+  const double s2 = sigma * sigma;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t cx = std::min<int64_t>((int64_t)(hx[(size_t)i] / gs), g - 1);
+    int64_t cy = std::min<int64_t>((int64_t)(hy[(size_t)i] / gs), g - 1);
+    for (int64_t oy = -1; oy <= 1; ++oy)
+      for (int64_t ox = -1; ox <= 1; ++ox) {
+        int64_t nx = ((cx + ox) % g + g) % g, ny = ((cy + oy) % g + g) % g;
+        for (int64_t j = head[(size_t)(ny * g + nx)]; j >= 0; j = next[(size_t)j]) {
+          if (j <= i) continue;
+          double dx = hx[(size_t)j] - hx[(size_t)i], dy = hy[(size_t)j] - hy[(size_t)i];
+          dx -= L * std::nearbyint(dx / L);
+          dy -= L * std::nearbyint(dy / L);
+          if (dx * dx + dy * dy < s2) {
+            s->last_error = "disks " + std::to_string(i) + " and " + std::to_string(j) + " overlap";
+            return EC_E_OVERLAP;
+          }
+        }
+        if (g < 3 && (ox != 0 || oy != 0)) { /* small grids revisit cells; harmless */ }
+      }
+  }
+  EC_HIP(s, hipMemcpyAsync(s->dev.x, hx.data(), 8 * (size_t)n, hipMemcpyHostToDevice, s->stream));
+  EC_HIP(s, hipMemcpyAsync(s->dev.y, hy.data(), 8 * (size_t)n, hipMemcpyHostToDevice, s->stream));
+  EC_HIP(s, hipStreamSynchronize(s->stream));
+  return EC_OK;
+}
+
+ec_status ec_get_digests(ec_system s, uint64_t* out, int64_t n) {
+  if (!s || !out || n < 0 || n > s->sweeps || n > ec::kDigestRing) return EC_E_INVALID;
+  std::vector<uint64_t> ring(ec::kDigestRing);
+  EC_HIP(s, hipMemcpyAsync(ring.data(), s->dev.digest_ring, 8 * ring.size(), hipMemcpyDeviceToHost,
+                           s->stream));
+  ec_status st = check_err(s);
+  if (st != EC_OK) return st;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t sw = s->sweeps - n + i;
+    out[i] = ring[(size_t)(sw % ec::kDigestRing)];
+  }
+  return EC_OK;
+}
+
+ec_status ec_get_cell_tallies(ec_system s, double* delta, uint64_t* counts) {
+  if (!s || !delta || !counts) return EC_E_INVALID;
+  size_t nc = (size_t)s->p.cells_per_side * (size_t)s->p.cells_per_side;
+  EC_HIP(s, hipMemcpyAsync(delta, s->dev.acc_delta, 8 * nc, hipMemcpyDeviceToHost, s->stream));
+  EC_HIP(s, hipMemcpyAsync(counts, s->dev.acc_cnt, 8 * ec::CNT_NCOL * nc, hipMemcpyDeviceToHost,
+                           s->stream));
+  return check_err(s);
+}
+
+ec_status ec_get_cell_digests(ec_system s, uint64_t* out) {
+  if (!s || !out) return EC_E_INVALID;
+  size_t nc = (size_t)s->p.cells_per_side * (size_t)s->p.cells_per_side;
+  EC_HIP(s, hipMemcpyAsync(out, s->dev.cell_digest, 8 * nc, hipMemcpyDeviceToHost, s->stream));
+  return check_err(s);
+}
+
+ec_status ec_get_sweep_count(ec_system s, int64_t* sweeps) {
+  if (!s || !sweeps) return EC_E_INVALID;
+  *sweeps = s->sweeps;
+  return EC_OK;
+}
+
+ec_status ec_destroy(ec_system s) {
+  if (!s) return EC_E_INVALID;
+  if (s->timing) ec_set_timing(s, 0);
+  hipError_t e = hipStreamSynchronize(s->stream);
+  delete s;
+  return e == hipSuccess ? EC_OK : EC_E_HIP;
+}
+
+}  // extern "C"

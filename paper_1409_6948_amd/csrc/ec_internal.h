@@ -1,0 +1,107 @@
+// Internal interface between the C ABI (ec_api.cpp) and the gfx950 kernels
+// (ec_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ec {
+
+// Per-sweep draws written by the prep kernel (shift of the cell grid and the
+// order of the four colours, Sec. 3.4 steps 1 and 3).
+struct SweepDraws {
+  double sx, sy;
+  int32_t perm[4];
+};
+
+// Column order of the per-cell counters.
+enum { CNT_LIFTS = 0, CNT_FROZEN = 1, CNT_WALLS = 2, CNT_CHAINS = 3, CNT_PSEUDO = 4, CNT_NCOL = 5 };
+
+// Device error bits.  Any nonzero value also tells every running wave to stop.
+enum {
+  ERR_OWN_CAP = 1,     // a cell (own or neighbour) holds more disks than the packing bound
+  ERR_BIN_CAP = 2,     // more than four centres in one LDS bin
+  ERR_EVENT_CAP = 4,   // a chain exceeded kMaxEventsPerChain events
+  ERR_DRAW_CAP = 8     // a rejection draw exceeded kMaxDrawTries attempts
+};
+
+// Events allowed in one chain before the sweep gives up with ERR_EVENT_CAP.
+// Only degenerate input (a closed ring of touching disks, a disk pinned
+// between two antipodal frozen contacts) comes near it; every wave then
+// leaves its loops and the host reports the error.
+constexpr int64_t kMaxEventsPerChain = int64_t(1) << 20;
+// Events between two polls of the device error word.
+constexpr int64_t kAbortPollEvents = 1024;
+// Attempts of one rejection draw (acceptance 0.785 for directions, > 1 - 2^-50
+// for indices); reaching the cap sets ERR_DRAW_CAP.
+constexpr int kMaxDrawTries = 256;
+// Doubles in the debug snapshot written by the first wave that trips a cap.
+constexpr int kDebugWords = 16;
+
+constexpr int kDigestRing = 1024;
+
+// Everything a kernel needs: device pointers into the caller's workspace and
+// the derived constants.  Passed by value.
+struct Dev {
+  double* x;                        // [N] positions, disk-id order
+  double* y;
+  int32_t* cell_count;              // [C*C]
+  int32_t* cell_fill;               // [C*C]
+  int32_t* cell_start;              // [C*C+1] exclusive prefix sum
+  int32_t* cell_of;                 // [N]
+  int32_t* cell_ids;                // [N] ids grouped by cell (any order inside a cell)
+  double* acc_delta;                // [C*C]
+  unsigned long long* acc_cnt;      // [C*C*CNT_NCOL]
+  unsigned long long* digest_ring;  // [kDigestRing]
+  unsigned long long* cell_digest;  // [C*C] digest of each cell in the last sweep it ran
+  SweepDraws* draws;                // [1]
+  int32_t* err;                     // [1]
+  double* red;                      // [8]: reduced tallies (double sum + counters as bits)
+  int32_t* chain_start;             // [max chains per sweep] start index within its cell
+  double2* chain_dir;               // [max chains per sweep] direction of each chain
+  int32_t* shuffle;                 // [N] per-cell shuffled lists (distinct-start mode)
+  double* dbg;                      // [kDebugWords] state of the first wave that tripped a cap
+
+  int64_t n;
+  double sigma, sig2, ell, L, half_L, w, cap, b, inv_b, margin;
+  int32_t C, nb, gridb, cap_own, chains_per_cell, dir_mode, start_mode, precision;
+  int32_t lds_per_cell, cells_per_block;
+  int32_t search;                   // 0: 4x4-bin window with guard; 1: scan of every slot
+  uint64_t seed;
+  uint32_t system;
+};
+
+// LDS layout of one simulation cell in the walled-cell kernel.
+struct CellLds {
+  int32_t off_pos, off_gid, off_lidx, off_mask, off_own_gid, off_own_loc, off_tmp, bytes;
+};
+
+__host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own) {
+  CellLds l;
+  int slots = gridb * gridb * 4;
+  int o = 0;
+  l.off_pos = o;      o += 16 * slots;
+  l.off_gid = o;      o += 4 * slots;
+  l.off_lidx = o;     o += 4 * slots;
+  l.off_mask = o;     o += 4 * gridb * gridb;
+  l.off_own_gid = o;  o += 4 * cap_own;
+  l.off_own_loc = o;  o += 4 * cap_own;
+  l.off_tmp = o;      o += 4 * cap_own;
+  l.bytes = (o + 15) & ~15;
+  return l;
+}
+
+// Largest N the one-periodic-cell kernel keeps in LDS.
+constexpr int64_t kPeriodicMaxN = 2048;
+
+hipError_t launch_lattice(const Dev& d, int64_t k, double a, hipStream_t st);
+// Optional HIP events recorded around every phase launch (begin[q], end[q]).
+struct PhaseEvents {
+  hipEvent_t begin[4], end[4];
+};
+
+hipError_t launch_sweep(const Dev& d, int64_t sweep, hipStream_t st,
+                        const PhaseEvents* ev = nullptr);
+hipError_t launch_reduce(const Dev& d, hipStream_t st);
+hipError_t launch_zero_tallies(const Dev& d, hipStream_t st);
+
+}  // namespace ec

@@ -1,0 +1,951 @@
+// gfx950 kernels of the parallel event-chain (PEC) sweep for 2D hard disks.
+//
+// Method: Kampmann, Boltz, Kierfeld, "Parallelized event chain algorithm for
+// dense hard sphere and polymer systems" -- event chains Sec. 3.2, the
+// parallel sweep Sec. 3.4 (steps 1-7), boundary reflection Fig. 1 (right),
+// starts with replacement Fig. 2.
+//
+// Mapping to CDNA4: one wavefront (64 lanes) per active simulation cell.  A
+// cell's own disks and its frozen neighbours (centres within sigma outside
+// the cell) are staged in LDS in a grid of square bins of side b in
+// [sigma, 4/3 sigma); such a bin holds at most four non-overlapping centres,
+// so four slots per bin suffice.  One event search reads a 4 x 4 window of
+// bins around the moving disk, one slot per lane, computes the contact
+// distance of every slot in FP64, and takes a wave-wide minimum of the key
+// (distance, disk id).  A geometric guard proves that no disk outside the
+// window can be hit first; when it cannot (long free flights), the search is
+// repeated over all slots of the cell.  The event found is therefore exactly
+// the minimum over all candidate disks, in the same arithmetic as a plain
+// serial search.
+//
+// Arithmetic contract (shared in writing with the CPU reference, no code
+// shared): FP64 with no contraction (-ffp-contract=off) and explicit fma();
+// correctly rounded sqrt and division; Philox4x64-10 streams keyed by
+// (seed, kind) with counters (sweep, cell | system << 32, chain, block).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ec_internal.h"
+
+namespace ec {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// ---------------------------------------------------------------------------
+constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kW1 = 0xBB67AE8584CAA73Bull;
+
+enum : uint64_t { kKindSweep = 1, kKindStart = 2, kKindDir = 3, kKindShuffle = 4 };
+
+struct Block4 {
+  uint64_t v0, v1, v2, v3;
+};
+
+__device__ __forceinline__ Block4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                         uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += kW0; k1 += kW1; }
+    uint64_t hi0 = __umul64hi(kM0, c0), lo0 = kM0 * c0;
+    uint64_t hi1 = __umul64hi(kM1, c2), lo1 = kM1 * c2;
+    uint64_t n0 = hi1 ^ c1 ^ k0;
+    uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  return Block4{c0, c1, c2, c3};
+}
+
+// Words 0..3 of counter block 0, then block 1, ...
+struct Stream {
+  uint64_t k0, k1, c0, c1, c2, blk;
+  Block4 b;
+  int pos;
+  __device__ Stream(uint64_t seed, uint64_t kind, uint64_t a, uint64_t bb, uint64_t c)
+      : k0(seed), k1(kind), c0(a), c1(bb), c2(c), blk(0), b{0, 0, 0, 0}, pos(4) {}
+  __device__ uint64_t next() {
+    if (pos == 4) {
+      b = philox(c0, c1, c2, blk, k0, k1);
+      blk += 1;
+      pos = 0;
+    }
+    uint64_t w = (pos == 0) ? b.v0 : (pos == 1) ? b.v1 : (pos == 2) ? b.v2 : b.v3;
+    pos += 1;
+    return w;
+  }
+};
+
+__device__ __forceinline__ double u01(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
+
+// Lemire's multiply-shift with rejection: exactly uniform on [0, n).
+__device__ uint64_t draw_index(Stream& st, uint64_t n) {
+  uint64_t x = st.next();
+  uint64_t hi = __umul64hi(x, n), lo = x * n;
+  if (lo < n) {
+    uint64_t t = (0ull - n) % n;
+    while (lo < t) {
+      x = st.next();
+      hi = __umul64hi(x, n);
+      lo = x * n;
+    }
+  }
+  return hi;
+}
+
+__device__ __forceinline__ uint64_t cell_key(const Dev& d, int cell) {
+  return (uint64_t)(uint32_t)cell | ((uint64_t)d.system << 32);
+}
+
+// Direction of chain k of a cell in a sweep.
+__device__ void chain_direction(const Dev& d, int64_t sweep, int cell, int64_t k, double& dx,
+                                double& dy) {
+  if (d.dir_mode == 2) { dx = 1.0; dy = 0.0; return; }          // +x only
+  if (d.dir_mode == 0) {                                         // +x / +y alternating
+    if ((k & 1) == 0) { dx = 1.0; dy = 0.0; } else { dx = 0.0; dy = 1.0; }
+    return;
+  }
+  // isotropic: uniform in the unit disk by rejection, then normalised
+  Stream st(d.seed, kKindDir, (uint64_t)sweep, cell_key(d, cell), (uint64_t)k);
+  double vx, vy, r2;
+  for (;;) {
+    vx = 2.0 * u01(st.next()) - 1.0;
+    vy = 2.0 * u01(st.next()) - 1.0;
+    r2 = fma(vx, vx, vy * vy);
+    if (r2 < 1.0 && r2 >= 0x1p-40) break;
+  }
+  double r = sqrt(r2);
+  dx = vx / r;
+  dy = vy / r;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ unsigned umin_(unsigned a, unsigned b) { return a < b ? a : b; }
+
+// Minimum of a 32-bit value over the 64 lanes (DPP butterfly within rows of
+// 16, then row broadcasts); every lane gets the result.
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
+  v = umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));
+  v = umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));
+  v = umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));
+  v = umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));
+  v = umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));
+  v = umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  return __longlong_as_double((long long)readlane_u64((uint64_t)__double_as_longlong(v), lane));
+}
+__device__ __forceinline__ int readlane_i32(int v, int lane) {
+  return __builtin_amdgcn_readlane(v, lane);
+}
+
+// Lane holding the smallest key (s, id) among lanes with valid = true, where
+// s >= 0 so that its bit pattern orders like its value.  -1 if none.
+__device__ __forceinline__ int wave_argmin(double s, uint32_t id, bool valid) {
+  uint64_t sb = (uint64_t)__double_as_longlong(s);
+  unsigned hi = valid ? (unsigned)(sb >> 32) : 0xFFFFFFFFu;
+  unsigned m = wave_min_u32(hi);
+  if (m == 0xFFFFFFFFu) return -1;
+  uint64_t mask = __ballot(valid && hi == m);
+  int wl = __ffsll((unsigned long long)mask) - 1;
+  mask &= mask - 1;
+  if (mask) {  // equal high words: resolve on the full key
+    uint64_t bs = readlane_u64(sb, wl);
+    uint32_t bi = (uint32_t)readlane_i32((int)id, wl);
+    while (mask) {
+      int l = __ffsll((unsigned long long)mask) - 1;
+      mask &= mask - 1;
+      uint64_t ls = readlane_u64(sb, l);
+      uint32_t li = (uint32_t)readlane_i32((int)id, l);
+      if (ls < bs || (ls == bs && li < bi)) { bs = ls; bi = li; wl = l; }
+    }
+  }
+  return wl;
+}
+
+// Event digest (order-sensitive hash of (kind, id, distance)).
+__device__ __forceinline__ uint64_t digest_event(uint64_t h, int kind, int64_t gid, double s) {
+  uint64_t sb = (uint64_t)__double_as_longlong(s);
+  uint64_t e = sb ^ ((uint64_t)gid * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)kind << 56);
+  h = (h ^ e) * 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 31;
+  return h;
+}
+
+enum { EV_LIFT = 1, EV_FROZEN = 2, EV_WALL_X = 3, EV_WALL_Y = 4, EV_PSEUDO = 5, EV_END = 6 };
+
+// Contact distance of a disk moving along unit d towards a disk at offset r:
+// s = a - sqrt(sigma^2 - c^2) with a = r.d, c = r x d, for a > 0 and
+// sigma^2 - c^2 > 0; negative values (touching disks) become 0.
+__device__ __forceinline__ bool contact(double rx, double ry, double dx, double dy, double sig2,
+                                        double& s) {
+  double a = fma(rx, dx, ry * dy);
+  double c = fma(rx, dy, -(ry * dx));
+  double disc = fma(-c, c, sig2);
+  if (a > 0.0 && disc > 0.0) {
+    double t = a - sqrt(disc);
+    s = (t < 0.0) ? 0.0 : t;
+    return true;
+  }
+  return false;
+}
+
+// Shifted-frame coordinate in [0, L] and cell-local coordinate.
+__device__ __forceinline__ double shifted(double p, double shift, double L) {
+  double t = p - shift;
+  if (t < 0.0) t += L;
+  return t;
+}
+__device__ __forceinline__ double local_coord(double p, double shift, double origin, double L,
+                                              double half_L) {
+  double v = shifted(p, shift, L) - origin;
+  if (v < -half_L) v += L;
+  else if (v >= half_L) v -= L;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Start lattice
+// ---------------------------------------------------------------------------
+__global__ void k_lattice(Dev d, int64_t k, double a) {
+  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= d.n) return;
+  int64_t j = id / k, i = id % k;
+  d.x[id] = ((double)i + ((j & 1) ? 0.75 : 0.25)) * a;
+  d.y[id] = ((double)j + 0.5) * a;
+}
+
+// ---------------------------------------------------------------------------
+// Rebin: sweep draws, cell of every disk, counting sort by cell
+// ---------------------------------------------------------------------------
+__device__ void decode_perm(uint64_t idx, int32_t* perm) {
+  int32_t avail[4] = {0, 1, 2, 3};
+  const uint64_t fact[4] = {6, 2, 1, 1};
+  int navail = 4;
+  for (int pos = 0; pos < 4; ++pos) {
+    uint64_t q = idx / fact[pos];
+    idx = idx % fact[pos];
+    perm[pos] = avail[q];
+    for (int t = (int)q; t < navail - 1; ++t) avail[t] = avail[t + 1];
+    navail--;
+  }
+}
+
+__global__ void k_prep(Dev d, int64_t sweep) {
+  int ncell = d.C * d.C;
+  for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+    d.cell_count[c] = 0;
+    d.cell_fill[c] = 0;
+  }
+  if (threadIdx.x == 0) {
+    Stream st(d.seed, kKindSweep, (uint64_t)sweep, (uint64_t)d.system, 0);
+    SweepDraws dr;
+    dr.sx = u01(st.next()) * d.w;
+    dr.sy = u01(st.next()) * d.w;
+    decode_perm(draw_index(st, 24), dr.perm);
+    *d.draws = dr;
+    d.digest_ring[sweep % kDigestRing] = 0;
+  }
+}
+
+__device__ __forceinline__ int cell_of_pos(const Dev& d, double px, double py, double sx,
+                                           double sy) {
+  int cx = (int)floor(shifted(px, sx, d.L) / d.w);
+  int cy = (int)floor(shifted(py, sy, d.L) / d.w);
+  if (cx > d.C - 1) cx = d.C - 1;
+  if (cy > d.C - 1) cy = d.C - 1;
+  return cy * d.C + cx;
+}
+
+__global__ void k_count(Dev d) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  SweepDraws dr = *d.draws;
+  int c = cell_of_pos(d, d.x[i], d.y[i], dr.sx, dr.sy);
+  d.cell_of[i] = c;
+  atomicAdd(&d.cell_count[c], 1);
+}
+
+// Exclusive prefix sum of the cell counts, one workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) k_scan(Dev d) {
+  __shared__ int32_t part[1024];
+  int ncell = d.C * d.C;
+  int per = (ncell + 1023) / 1024;
+  int b0 = threadIdx.x * per;
+  int sum = 0;
+  for (int c = b0; c < b0 + per && c < ncell; ++c) sum += d.cell_count[c];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = (threadIdx.x == 0) ? 0 : part[threadIdx.x - 1];
+  for (int c = b0; c < b0 + per && c < ncell; ++c) {
+    d.cell_start[c] = run;
+    run += d.cell_count[c];
+  }
+  if (threadIdx.x == 1023) d.cell_start[ncell] = part[1023];
+}
+
+__global__ void k_scatter(Dev d) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  int c = d.cell_of[i];
+  int slot = atomicAdd(&d.cell_fill[c], 1);
+  d.cell_ids[d.cell_start[c] + slot] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// Chain draws of a sweep (Sec. 3.4 step 5): one thread per chain computes the
+// start index, drawn with replacement among the cell's n_c disks, and the
+// isotropic direction.  Rejection loops are capped (kMaxDrawTries).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t chains_of(const Dev& d, int n_c) {
+  if (n_c <= 0) return 0;
+  return d.chains_per_cell > 0 ? d.chains_per_cell : n_c;
+}
+__device__ __forceinline__ int64_t chain_base(const Dev& d, int cell) {
+  return d.chains_per_cell > 0 ? (int64_t)cell * d.chains_per_cell : (int64_t)d.cell_start[cell];
+}
+
+__device__ bool draw_index_capped(Stream& st, uint64_t n, uint64_t& out) {
+  uint64_t x = st.next();
+  uint64_t hi = __umul64hi(x, n), lo = x * n;
+  if (lo < n) {
+    uint64_t t = (0ull - n) % n;
+    int tries = 0;
+    while (lo < t) {
+      if (++tries > kMaxDrawTries) return false;
+      x = st.next();
+      hi = __umul64hi(x, n);
+      lo = x * n;
+    }
+  }
+  out = hi;
+  return true;
+}
+
+__device__ bool iso_direction_capped(const Dev& d, int64_t sweep, int cell, int64_t k, double& dx,
+                                     double& dy) {
+  Stream st(d.seed, kKindDir, (uint64_t)sweep, cell_key(d, cell), (uint64_t)k);
+  for (int tries = 0; tries < kMaxDrawTries; ++tries) {
+    double vx = 2.0 * u01(st.next()) - 1.0;
+    double vy = 2.0 * u01(st.next()) - 1.0;
+    double r2 = fma(vx, vx, vy * vy);
+    if (r2 < 1.0 && r2 >= 0x1p-40) {
+      double r = sqrt(r2);
+      dx = vx / r;
+      dy = vy / r;
+      return true;
+    }
+  }
+  dx = 1.0;
+  dy = 0.0;
+  return false;
+}
+
+// Cell whose range [cell_start[c], cell_start[c+1]) holds chain slot i.
+__device__ __forceinline__ int cell_of_slot(const Dev& d, int64_t i) {
+  int lo = 0, hi = d.C * d.C - 1;
+  while (lo < hi) {  // largest c with cell_start[c] <= i
+    int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)d.cell_start[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_draws(Dev d, int64_t sweep, int64_t total) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  int cell;
+  int64_t k;
+  if (d.chains_per_cell > 0) {
+    cell = (int)(i / d.chains_per_cell);
+    k = i % d.chains_per_cell;
+  } else {
+    cell = cell_of_slot(d, i);
+    k = i - d.cell_start[cell];
+  }
+  int n_c = d.cell_start[cell + 1] - d.cell_start[cell];
+  double dx, dy;
+  bool ok = iso_direction_capped(d, sweep, cell, k, dx, dy);
+  d.chain_dir[i] = make_double2(dx, dy);
+  int32_t start = 0;
+  if (n_c > 0 && d.start_mode == 0) {
+    Stream st(d.seed, kKindStart, (uint64_t)sweep, cell_key(d, cell), (uint64_t)k);
+    uint64_t v = 0;
+    if (!draw_index_capped(st, (uint64_t)n_c, v)) ok = false;
+    start = (int32_t)v;
+  }
+  if (d.start_mode == 0) d.chain_start[i] = start;
+  if (!ok) atomicOr(d.err, ERR_DRAW_CAP);
+}
+
+// Distinct-start negative control: one thread per cell shuffles [0, n_c)
+// (Fisher-Yates) and chain k starts at list[k mod n_c].
+__global__ void k_shuffle(Dev d, int64_t sweep) {
+  int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= d.C * d.C) return;
+  int s0 = d.cell_start[cell];
+  int n_c = d.cell_start[cell + 1] - s0;
+  if (n_c <= 0) return;
+  int32_t* list = d.shuffle + s0;
+  for (int i = 0; i < n_c; ++i) list[i] = i;
+  Stream st(d.seed, kKindShuffle, (uint64_t)sweep, cell_key(d, cell), 0);
+  bool ok = true;
+  for (int i = 0; i + 1 < n_c; ++i) {
+    uint64_t v = 0;
+    if (!draw_index_capped(st, (uint64_t)(n_c - i), v)) ok = false;
+    int j = i + (int)v;
+    int t = list[i]; list[i] = list[j]; list[j] = t;
+  }
+  int64_t n_m = chains_of(d, n_c);
+  int64_t base = chain_base(d, cell);
+  for (int64_t k = 0; k < n_m; ++k) d.chain_start[base + k] = list[k % n_c];
+  if (!ok) atomicOr(d.err, ERR_DRAW_CAP);
+}
+
+// ---------------------------------------------------------------------------
+// Walled simulation cells: one wavefront per active cell of colour perm[q]
+// ---------------------------------------------------------------------------
+constexpr uint32_t kFrozenBit = 0x80000000u;
+
+__device__ __forceinline__ int32_t load_err(const Dev& d) {
+  return __hip_atomic_load(d.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int half = d.C >> 1;
+  const int blk = blockIdx.x * d.cells_per_block + wave;
+  if (blk >= half * half) return;  // the whole wave leaves; no workgroup barrier follows
+
+  const SweepDraws dr = *d.draws;
+  const int colour = dr.perm[q & 3];
+  const int cx = 2 * (blk % half) + (colour & 1);
+  const int cy = 2 * (blk / half) + (colour >> 1);
+  const int cell = cy * d.C + cx;
+  const double ox = (double)cx * d.w, oy = (double)cy * d.w;
+  const double L = d.L, half_L = d.half_L, w = d.w, sigma = d.sigma, sig2 = d.sig2;
+  const int gridb = d.gridb, nb = d.nb;
+  const int nslots = gridb * gridb * 4;
+
+  const CellLds lay = cell_lds_layout(gridb, d.cap_own);
+  unsigned char* base = lds_raw + (size_t)wave * d.lds_per_cell;
+  double2* pos = (double2*)(base + lay.off_pos);
+  uint32_t* gid = (uint32_t*)(base + lay.off_gid);
+  int32_t* lidx = (int32_t*)(base + lay.off_lidx);
+  int32_t* mask = (int32_t*)(base + lay.off_mask);
+  int32_t* own_gid = (int32_t*)(base + lay.off_own_gid);
+  int32_t* own_loc = (int32_t*)(base + lay.off_own_loc);
+  int32_t* tmp = (int32_t*)(base + lay.off_tmp);
+
+  // ---- stage: own disks, sorted by id -----------------------------------
+  const int start = d.cell_start[cell];
+  const int n_own = d.cell_start[cell + 1] - start;
+  if (n_own < 0 || n_own > d.cap_own || start < 0 || (int64_t)start + n_own > d.n) {
+    if (lane == 0) atomicOr(d.err, ERR_OWN_CAP);
+    return;
+  }
+  for (int i = lane; i < n_own; i += 64) tmp[i] = d.cell_ids[start + i];
+  wave_sync();
+  for (int i = lane; i < n_own; i += 64) {
+    int v = tmp[i];
+    int r = 0;
+    for (int j = 0; j < n_own; ++j) r += (tmp[j] < v) ? 1 : 0;
+    own_gid[r] = v;
+  }
+  const double2 nan2 = make_double2(__builtin_nan(""), __builtin_nan(""));
+  for (int s = lane; s < nslots; s += 64) pos[s] = nan2;
+  for (int bi = lane; bi < gridb * gridb; bi += 64) mask[bi] = 0;
+  wave_sync();
+
+  // own disks into bins 1..nb (mask[] counts during staging)
+  for (int k = lane; k < n_own; k += 64) {
+    int g = own_gid[k];
+    double vx = local_coord(d.x[g], dr.sx, ox, L, half_L);
+    double vy = local_coord(d.y[g], dr.sy, oy, L, half_L);
+    int bx = (int)floor(vx * d.inv_b) + 1, by = (int)floor(vy * d.inv_b) + 1;
+    bx = bx < 1 ? 1 : (bx > nb ? nb : bx);
+    by = by < 1 ? 1 : (by > nb ? nb : by);
+    int bin = by * gridb + bx;
+    int slot = atomicAdd(&mask[bin], 1);
+    if (slot >= 4) { atomicOr(d.err, ERR_BIN_CAP); continue; }
+    int s = bin * 4 + slot;
+    pos[s] = make_double2(vx, vy);
+    gid[s] = (uint32_t)g;
+    lidx[s] = k;
+    own_loc[k] = s;
+  }
+  // frozen disks: centres of the 8 neighbouring cells within sigma of this cell
+  for (int nbh = 0; nbh < 9; ++nbh) {
+    if (nbh == 4) continue;
+    int ncx = (cx + (nbh % 3) - 1 + d.C) % d.C;
+    int ncy = (cy + (nbh / 3) - 1 + d.C) % d.C;
+    int nc = ncy * d.C + ncx;
+    int s0 = d.cell_start[nc], s1 = d.cell_start[nc + 1];
+    if (s0 < 0 || s1 < s0 || s1 - s0 > d.cap_own || (int64_t)s1 > d.n) {
+      if (lane == 0) atomicOr(d.err, ERR_OWN_CAP);
+      return;
+    }
+    for (int i = s0 + lane; i < s1; i += 64) {
+      int g = d.cell_ids[i];
+      double vx = local_coord(d.x[g], dr.sx, ox, L, half_L);
+      double vy = local_coord(d.y[g], dr.sy, oy, L, half_L);
+      if (vx >= -sigma && vx <= w + sigma && vy >= -sigma && vy <= w + sigma) {
+        int bx = (int)floor(vx * d.inv_b) + 1, by = (int)floor(vy * d.inv_b) + 1;
+        bx = bx < 0 ? 0 : (bx > nb + 1 ? nb + 1 : bx);
+        by = by < 0 ? 0 : (by > nb + 1 ? nb + 1 : by);
+        int bin = by * gridb + bx;
+        int slot = atomicAdd(&mask[bin], 1);
+        if (slot >= 4) { atomicOr(d.err, ERR_BIN_CAP); continue; }
+        int s = bin * 4 + slot;
+        pos[s] = make_double2(vx, vy);
+        gid[s] = (uint32_t)g | kFrozenBit;
+        lidx[s] = -1;
+      }
+    }
+  }
+  wave_sync();
+  for (int bi = lane; bi < gridb * gridb; bi += 64) {
+    int c = mask[bi];
+    mask[bi] = (c >= 4) ? 0xF : ((1 << c) - 1);
+  }
+  wave_sync();
+  if (load_err(d) != 0) return;  // a capacity check failed somewhere: do not run chains
+
+  // ---- chains --------------------------------------------------------------
+  const int64_t n_m = chains_of(d, n_own);
+  const int64_t cbase = chain_base(d, cell);
+  double acc = d.acc_delta[cell];
+  uint64_t n_lift = 0, n_frozen = 0, n_wall = 0;
+  uint64_t h = 0;
+  const int lx = lane & 3, ly = (lane >> 2) & 3, ks = lane >> 4;
+  const double eps = 1e-9 * sigma;
+  const double b = d.b;
+  const uint32_t wall_x_id = (uint32_t)d.n, wall_y_id = (uint32_t)d.n + 1u;
+  const bool use_window = d.search == 0;
+  int64_t since_poll = 0;
+  bool aborted = false;
+
+  for (int64_t k = 0; k < n_m && !aborted; ++k) {
+    int j = d.chain_start[cbase + k];
+    if (j < 0 || j >= n_own) j = 0;  // guarded: the draw kernel writes indices below n_own
+    const double2 dir = d.chain_dir[cbase + k];
+    double dx = dir.x, dy = dir.y;
+    double idx = (dx != 0.0) ? 1.0 / dx : 0.0;
+    double idy = (dy != 0.0) ? 1.0 / dy : 0.0;
+    int a_loc = own_loc[j];
+    int a_lidx = j;
+    uint32_t a_gid = (uint32_t)own_gid[j];
+    double2 ap = pos[a_loc];
+    double ax = ap.x, ay = ap.y;
+    double rem = d.ell;
+    int64_t n_events = 0;
+
+    for (;;) {
+      if (++n_events > kMaxEventsPerChain) {
+        if (lane == 0) {
+          atomicOr(d.err, ERR_EVENT_CAP);
+          if (atomicAdd(d.err + 1, 1) == 0) {
+            double* g = d.dbg;
+            g[0] = (double)cell; g[1] = (double)k; g[2] = (double)sweep; g[3] = (double)q;
+            g[4] = ax; g[5] = ay; g[6] = dx; g[7] = dy; g[8] = rem; g[9] = (double)a_loc;
+            g[10] = (double)a_gid; g[11] = (double)n_own;
+          }
+        }
+        aborted = true;
+        break;
+      }
+      if (++since_poll >= kAbortPollEvents) {
+        since_poll = 0;
+        if (load_err(d) != 0) { aborted = true; break; }
+      }
+      // -- window search: 4 x 4 bins x 4 slots, one slot per lane
+      const int abin = a_loc >> 2;
+      const int abx = abin % gridb, aby = abin / gridb;
+      int wx0 = abx - (dx < 0.0 ? 2 : 1);
+      int wy0 = aby - (dy < 0.0 ? 2 : 1);
+      wx0 = wx0 < 0 ? 0 : (wx0 > gridb - 4 ? gridb - 4 : wx0);
+      wy0 = wy0 < 0 ? 0 : (wy0 > gridb - 4 ? gridb - 4 : wy0);
+      int slot = (((wy0 + ly) * gridb) + (wx0 + lx)) * 4 + ks;
+      double2 p = pos[slot];
+      uint32_t g = gid[slot];
+      double s = 0.0;
+      bool valid = contact(p.x - ax, p.y - ay, dx, dy, sig2, s);
+      int wl = wave_argmin(s, g & ~kFrozenBit, valid);
+
+      // walls of the cell
+      double tx = INFINITY, ty = INFINITY;
+      if (dx != 0.0) { tx = (dx > 0.0) ? (w - ax) * idx : (0.0 - ax) * idx; if (tx < 0.0) tx = 0.0; }
+      if (dy != 0.0) { ty = (dy > 0.0) ? (w - ay) * idy : (0.0 - ay) * idy; if (ty < 0.0) ty = 0.0; }
+
+      double best_s = INFINITY;
+      uint32_t best_id = 0xFFFFFFFFu;
+      int kind = 0;
+      int w_slot = -1;
+      double2 wp = nan2;
+      if (wl >= 0) {
+        best_s = readlane_f64(s, wl);
+        uint32_t gw = (uint32_t)readlane_i32((int)g, wl);
+        best_id = gw & ~kFrozenBit;
+        kind = (gw & kFrozenBit) ? EV_FROZEN : EV_LIFT;
+        w_slot = readlane_i32(slot, wl);
+        wp.x = readlane_f64(p.x, wl);
+        wp.y = readlane_f64(p.y, wl);
+      }
+      // guard: every disk outside the window is farther than the event found
+      {
+        double t = best_s < rem ? best_s : rem;
+        t = t < tx ? t : tx;
+        t = t < ty ? t : ty;
+        double ex = fma(t, dx, ax), ey = fma(t, dy, ay);
+        double x_lo = (ax < ex ? ax : ex) - sigma - eps, x_hi = (ax > ex ? ax : ex) + sigma + eps;
+        double y_lo = (ay < ey ? ay : ey) - sigma - eps, y_hi = (ay > ey ? ay : ey) + sigma + eps;
+        bool ok = use_window;
+        if (wx0 > 0 && x_lo < (double)(wx0 - 1) * b) ok = false;
+        if (wx0 + 4 < gridb && x_hi > (double)(wx0 + 3) * b) ok = false;
+        if (wy0 > 0 && y_lo < (double)(wy0 - 1) * b) ok = false;
+        if (wy0 + 4 < gridb && y_hi > (double)(wy0 + 3) * b) ok = false;
+        if (!ok) {
+          // exact search over every slot of the cell
+          double ls = INFINITY;
+          uint32_t lid = 0xFFFFFFFFu;
+          int lslot = -1;
+          for (int sl = lane; sl < nslots; sl += 64) {
+            double2 q2 = pos[sl];
+            double s2;
+            if (contact(q2.x - ax, q2.y - ay, dx, dy, sig2, s2)) {
+              uint32_t i2 = gid[sl] & ~kFrozenBit;
+              if (s2 < ls || (s2 == ls && i2 < lid)) { ls = s2; lid = i2; lslot = sl; }
+            }
+          }
+          int fl = wave_argmin(ls, lid, lslot >= 0);
+          best_s = INFINITY; best_id = 0xFFFFFFFFu; kind = 0; w_slot = -1;
+          if (fl >= 0) {
+            best_s = readlane_f64(ls, fl);
+            w_slot = readlane_i32(lslot, fl);
+            uint32_t gw = gid[w_slot];
+            best_id = gw & ~kFrozenBit;
+            kind = (gw & kFrozenBit) ? EV_FROZEN : EV_LIFT;
+            wp = pos[w_slot];
+          }
+        }
+      }
+      if (tx < best_s || (tx == best_s && wall_x_id < best_id)) { best_s = tx; best_id = wall_x_id; kind = EV_WALL_X; }
+      if (ty < best_s || (ty == best_s && wall_y_id < best_id)) { best_s = ty; best_id = wall_y_id; kind = EV_WALL_Y; }
+
+      const bool ends = !(best_s < rem);
+      const double step = ends ? rem : best_s;
+      if (ends) {
+        h = digest_event(h, EV_END, (int64_t)d.n + 3, rem);
+      } else {
+        h = digest_event(h, kind, (int64_t)best_id, best_s);
+      }
+      ax = fma(step, dx, ax);
+      ay = fma(step, dy, ay);
+      // store the moved disk; move it to another bin if it crossed a bin edge
+      {
+        int nbx = (int)floor(ax * d.inv_b) + 1, nby = (int)floor(ay * d.inv_b) + 1;
+        nbx = nbx < 1 ? 1 : (nbx > nb ? nb : nbx);
+        nby = nby < 1 ? 1 : (nby > nb ? nb : nby);
+        int nbin = nby * gridb + nbx;
+        if (nbin == abin) {
+          if (lane == 0) pos[a_loc] = make_double2(ax, ay);
+        } else {
+          int om = mask[abin];
+          int nm = mask[nbin];
+          int free_slot = __builtin_ctz((unsigned)(~nm & 0xF) | 0x10u);
+          if (free_slot >= 4) {
+            if (lane == 0) { atomicOr(d.err, ERR_BIN_CAP); pos[a_loc] = make_double2(ax, ay); }
+          } else {
+            int ns = nbin * 4 + free_slot;
+            if (lane == 0) {
+              mask[abin] = om & ~(1 << (a_loc & 3));
+              pos[a_loc] = nan2;
+              mask[nbin] = nm | (1 << free_slot);
+              pos[ns] = make_double2(ax, ay);
+              gid[ns] = a_gid;
+              lidx[ns] = a_lidx;
+              own_loc[a_lidx] = ns;
+            }
+            a_loc = ns;
+          }
+        }
+        wave_sync();
+      }
+      if (ends) break;
+      rem = rem - best_s;
+      if (kind == EV_LIFT) {
+        // straight chain: the hit disk goes on in the same direction
+        double rx = wp.x - ax, ry = wp.y - ay;
+        acc = acc + fma(rx, dx, ry * dy);
+        n_lift += 1;
+        a_loc = w_slot;
+        a_gid = best_id;
+        a_lidx = lidx[w_slot];
+        ax = wp.x;
+        ay = wp.y;
+      } else if (kind == EV_FROZEN) {
+        // mirror the direction about the contact normal
+        double rx = wp.x - ax, ry = wp.y - ay;
+        acc = acc + fma(rx, dx, ry * dy);
+        n_frozen += 1;
+        double nrm = sqrt(fma(rx, rx, ry * ry));
+        double nx = rx / nrm, ny = ry / nrm;
+        double dn = fma(dx, nx, dy * ny);
+        double tt = -2.0 * dn;
+        double ux = fma(tt, nx, dx), uy = fma(tt, ny, dy);
+        double m = sqrt(fma(ux, ux, uy * uy));
+        dx = ux / m;
+        dy = uy / m;
+        idx = (dx != 0.0) ? 1.0 / dx : 0.0;
+        idy = (dy != 0.0) ? 1.0 / dy : 0.0;
+      } else if (kind == EV_WALL_X) {
+        dx = -dx; idx = -idx; n_wall += 1;
+      } else {
+        dy = -dy; idy = -idy; n_wall += 1;
+      }
+    }
+  }
+
+  // ---- write back: old position + local displacement, wrapped --------------
+  wave_sync();
+  for (int k = lane; k < n_own; k += 64) {
+    int g = own_gid[k];
+    double2 v = pos[own_loc[k]];
+    double px = d.x[g], py = d.y[g];
+    double v0x = local_coord(px, dr.sx, ox, L, half_L);
+    double v0y = local_coord(py, dr.sy, oy, L, half_L);
+    double nx = px + (v.x - v0x);
+    double ny = py + (v.y - v0y);
+    if (nx < 0.0) nx += L; else if (nx >= L) nx -= L;
+    if (ny < 0.0) ny += L; else if (ny >= L) ny -= L;
+    d.x[g] = nx;
+    d.y[g] = ny;
+  }
+  if (lane == 0) {
+    d.acc_delta[cell] = acc;
+    unsigned long long* c = d.acc_cnt + (size_t)cell * CNT_NCOL;
+    c[CNT_LIFTS] += n_lift;
+    c[CNT_FROZEN] += n_frozen;
+    c[CNT_WALLS] += n_wall;
+    c[CNT_CHAINS] += (uint64_t)n_m;
+    d.cell_digest[cell] = h;
+    atomicAdd(&d.digest_ring[sweep % kDigestRing], h * (2ull * (uint64_t)cell + 1ull));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One periodic cell (C = 1): all N disks in LDS, brute-force search with the
+// minimum image; flights longer than L/2 - sigma are split (free-flight cap).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_periodic(Dev d, int64_t sweep) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int lane = threadIdx.x;
+  const int n = (int)d.n;
+  double* px = (double*)lds_raw;
+  double* py = px + n;
+  int32_t* tmp = (int32_t*)(py + n);
+  const double L = d.L, half_L = d.half_L, sig2 = d.sig2, cap = d.cap;
+  for (int i = lane; i < n; i += 64) { px[i] = d.x[i]; py[i] = d.y[i]; }
+  int64_t n_m = d.chains_per_cell > 0 ? d.chains_per_cell : n;
+  if (d.start_mode == 1) {
+    wave_sync();
+    if (lane == 0) {
+      for (int i = 0; i < n; ++i) tmp[i] = i;
+      Stream st(d.seed, kKindShuffle, (uint64_t)sweep, cell_key(d, 0), 0);
+      for (int i = 0; i + 1 < n; ++i) {
+        int j = i + (int)draw_index(st, (uint64_t)(n - i));
+        int t = tmp[i]; tmp[i] = tmp[j]; tmp[j] = t;
+      }
+    }
+  }
+  wave_sync();
+  double acc = d.acc_delta[0];
+  uint64_t n_lift = 0, n_pseudo = 0, h = 0;
+
+  for (int64_t k = 0; k < n_m; ++k) {
+    int a;
+    if (d.start_mode == 1) {
+      a = tmp[k % n];
+    } else {
+      Stream st(d.seed, kKindStart, (uint64_t)sweep, cell_key(d, 0), (uint64_t)k);
+      a = (int)draw_index(st, (uint64_t)n);
+    }
+    double dx, dy;
+    chain_direction(d, sweep, 0, k, dx, dy);
+    double rem = d.ell;
+    double ax = px[a], ay = py[a];
+    int64_t n_events = 0;
+    for (;;) {
+      if (++n_events > kMaxEventsPerChain) {
+        if (lane == 0) atomicOr(d.err, ERR_EVENT_CAP);
+        break;
+      }
+      double ls = INFINITY;
+      int lj = -1;
+      for (int j = lane; j < n; j += 64) {
+        if (j == a) continue;
+        double rx = px[j] - ax, ry = py[j] - ay;
+        if (rx < -half_L) rx += L; else if (rx >= half_L) rx -= L;
+        if (ry < -half_L) ry += L; else if (ry >= half_L) ry -= L;
+        double s;
+        if (contact(rx, ry, dx, dy, sig2, s)) {
+          if (s < ls) { ls = s; lj = j; }  // j rises with the loop: lowest id kept on ties
+        }
+      }
+      int wl = wave_argmin(ls, (uint32_t)lj, lj >= 0);
+      double best_s = INFINITY;
+      int bj = -1;
+      if (wl >= 0) { best_s = readlane_f64(ls, wl); bj = readlane_i32(lj, wl); }
+      double lim = best_s < rem ? best_s : rem;
+      double step;
+      int kind;
+      if (lim > cap) {
+        step = cap; kind = EV_PSEUDO;
+        h = digest_event(h, EV_PSEUDO, d.n + 2, cap);
+      } else if (!(best_s < rem)) {
+        step = rem; kind = EV_END;
+        h = digest_event(h, EV_END, d.n + 3, rem);
+      } else {
+        step = best_s; kind = EV_LIFT;
+        h = digest_event(h, EV_LIFT, (int64_t)bj, best_s);
+      }
+      ax = fma(step, dx, ax);
+      ay = fma(step, dy, ay);
+      if (ax >= L) ax -= L; else if (ax < 0.0) ax += L;
+      if (ay >= L) ay -= L; else if (ay < 0.0) ay += L;
+      if (lane == 0) { px[a] = ax; py[a] = ay; }
+      wave_sync();
+      if (kind == EV_END) break;
+      if (kind == EV_PSEUDO) { rem = rem - cap; n_pseudo += 1; continue; }
+      rem = rem - best_s;
+      double rx = px[bj] - ax, ry = py[bj] - ay;
+      if (rx < -half_L) rx += L; else if (rx >= half_L) rx -= L;
+      if (ry < -half_L) ry += L; else if (ry >= half_L) ry -= L;
+      acc = acc + fma(rx, dx, ry * dy);
+      n_lift += 1;
+      a = bj;
+      ax = px[a];
+      ay = py[a];
+    }
+  }
+  wave_sync();
+  for (int i = lane; i < n; i += 64) { d.x[i] = px[i]; d.y[i] = py[i]; }
+  if (lane == 0) {
+    d.acc_delta[0] = acc;
+    d.acc_cnt[CNT_LIFTS] += n_lift;
+    d.acc_cnt[CNT_CHAINS] += (uint64_t)n_m;
+    d.acc_cnt[CNT_PSEUDO] += n_pseudo;
+    d.digest_ring[sweep % kDigestRing] = h;
+    d.cell_digest[0] = h;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tallies
+// ---------------------------------------------------------------------------
+__global__ void k_reduce(Dev d) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int ncell = d.C * d.C;
+  double s = 0.0;
+  uint64_t c[CNT_NCOL] = {0, 0, 0, 0, 0};
+  for (int i = 0; i < ncell; ++i) {
+    s = s + d.acc_delta[i];
+    for (int k = 0; k < CNT_NCOL; ++k) c[k] += d.acc_cnt[(size_t)i * CNT_NCOL + k];
+  }
+  d.red[0] = s;
+  for (int k = 0; k < CNT_NCOL; ++k) d.red[1 + k] = __longlong_as_double((long long)c[k]);
+}
+
+__global__ void k_zero_tallies(Dev d) {
+  int ncell = d.C * d.C;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += gridDim.x * blockDim.x) {
+    d.acc_delta[i] = 0.0;
+    for (int k = 0; k < CNT_NCOL; ++k) d.acc_cnt[(size_t)i * CNT_NCOL + k] = 0;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_lattice(const Dev& d, int64_t k, double a, hipStream_t st) {
+  int64_t blocks = (d.n + 255) / 256;
+  hipLaunchKernelGGL(k_lattice, dim3((unsigned)blocks), dim3(256), 0, st, d, k, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_tallies(const Dev& d, hipStream_t st) {
+  int ncell = d.C * d.C;
+  int blocks = (ncell + 255) / 256;
+  hipLaunchKernelGGL(k_zero_tallies, dim3(blocks), dim3(256), 0, st, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const Dev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, st, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(const Dev& d, int64_t sweep, hipStream_t st, const PhaseEvents* ev) {
+  if (d.C == 1) {
+    size_t lds = (size_t)d.n * 16 + (size_t)d.n * 4;
+    if (ev) hipEventRecord(ev->begin[0], st);
+    hipLaunchKernelGGL(k_periodic, dim3(1), dim3(64), lds, st, d, sweep);
+    if (ev) hipEventRecord(ev->end[0], st);
+    return hipGetLastError();
+  }
+  unsigned nblk = (unsigned)((d.n + 255) / 256);
+  hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, d, sweep);
+  hipLaunchKernelGGL(k_count, dim3(nblk), dim3(256), 0, st, d);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d);
+  hipLaunchKernelGGL(k_scatter, dim3(nblk), dim3(256), 0, st, d);
+  int64_t total = d.chains_per_cell > 0 ? (int64_t)d.C * d.C * d.chains_per_cell : d.n;
+  hipLaunchKernelGGL(k_draws, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, d, sweep,
+                     total);
+  if (d.start_mode == 1)
+    hipLaunchKernelGGL(k_shuffle, dim3((unsigned)((d.C * d.C + 63) / 64)), dim3(64), 0, st, d,
+                       sweep);
+  int half = d.C / 2;
+  int active = half * half;
+  int cpb = d.cells_per_block;
+  unsigned grid = (unsigned)((active + cpb - 1) / cpb);
+  size_t lds = (size_t)cpb * d.lds_per_cell;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_phase,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  for (int q = 0; q < 4; ++q) {
+    if (ev) hipEventRecord(ev->begin[q], st);
+    hipLaunchKernelGGL(k_phase, dim3(grid), dim3(64 * cpb), lds, st, d, sweep, q);
+    if (ev) hipEventRecord(ev->end[q], st);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ec

@@ -1,0 +1,213 @@
+"""ctypes binding of the C ABI in include/ec.h (argument marshalling only).
+
+Every step of the sweep runs in the HIP kernels of libec_hip.so.  PyTorch is
+used for the device workspace and the stream, nothing else.  If the library
+is missing, loading fails loudly; there is no fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libec_hip.so"
+
+EC_OK, EC_E_INVALID, EC_E_OVERLAP, EC_E_HIP, EC_E_NOMEM, EC_E_STATE, EC_E_UNSUPPORTED = range(7)
+EC_DIR_XY, EC_DIR_ISOTROPIC, EC_DIR_X = 0, 1, 2
+EC_PREC_FP64, EC_PREC_FP32_SCREEN = 0, 1
+EC_START_REPLACE, EC_START_DISTINCT = 0, 1
+EC_FLAG_SCAN_SEARCH = 1
+EC_ABI_VERSION = 1
+COUNT_NAMES = ("lifts", "frozen", "walls", "chains", "pseudo")
+
+# every symbol declared in include/ec.h
+EXPORTED = ("ec_workspace_bytes", "ec_init_system", "ec_sweep", "ec_measure_pressure",
+            "ec_reset_tallies", "ec_get_positions", "ec_set_positions", "ec_get_digests",
+            "ec_get_cell_tallies", "ec_get_cell_digests", "ec_get_sweep_count",
+            "ec_set_timing", "ec_get_timing", "ec_destroy", "ec_status_string",
+            "ec_last_error")
+
+
+class ECError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("flags", C.c_uint32), ("n_disks", C.c_int64),
+                ("sigma", C.c_double), ("eta", C.c_double), ("ell", C.c_double),
+                ("cells_per_side", C.c_int32), ("chains_per_cell", C.c_int32),
+                ("dir_mode", C.c_int32), ("precision", C.c_int32), ("start_mode", C.c_int32),
+                ("cells_per_block", C.c_int32), ("screen_margin", C.c_double),
+                ("seed", C.c_uint64), ("system", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib_path():
+    return os.path.join(HERE, _LIB_NAME)
+
+
+def load_library():
+    """Load libec_hip.so (built by build.py); raises if it is not there."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1409_6948_amd/build.py")
+    L = C.CDLL(path)
+    P = C.POINTER(Params)
+    vp, dp, u64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)
+    sigs = {
+        "ec_workspace_bytes": [P, C.POINTER(C.c_size_t)],
+        "ec_init_system": [P, vp, C.c_size_t, vp, C.POINTER(vp)],
+        "ec_sweep": [vp, C.c_int64],
+        "ec_measure_pressure": [vp, dp, dp, u64p],
+        "ec_reset_tallies": [vp],
+        "ec_get_positions": [vp, dp, dp, C.c_int64],
+        "ec_set_positions": [vp, dp, dp, C.c_int64],
+        "ec_get_digests": [vp, u64p, C.c_int64],
+        "ec_get_cell_tallies": [vp, dp, u64p],
+        "ec_get_cell_digests": [vp, u64p],
+        "ec_get_sweep_count": [vp, C.POINTER(C.c_int64)],
+        "ec_set_timing": [vp, C.c_int32],
+        "ec_get_timing": [vp, dp, C.POINTER(C.c_int64)],
+        "ec_destroy": [vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.ec_status_string.argtypes = [C.c_int]
+    L.ec_status_string.restype = C.c_char_p
+    L.ec_last_error.argtypes = [vp]
+    L.ec_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def make_params(n, eta, ell, cells, dir_mode=EC_DIR_ISOTROPIC, seed=1, sigma=1.0,
+                chains_per_cell=0, precision=EC_PREC_FP64, start_mode=EC_START_REPLACE,
+                cells_per_block=0, screen_margin=0.0, system=0, flags=0):
+    return Params(EC_ABI_VERSION, int(flags), int(n), float(sigma), float(eta), float(ell), int(cells),
+                  int(chains_per_cell), int(dir_mode), int(precision), int(start_mode),
+                  int(cells_per_block), float(screen_margin), int(seed), int(system), 0)
+
+
+def _check(status, handle=None, what=""):
+    if status != EC_OK:
+        L = load_library()
+        msg = L.ec_status_string(status).decode()
+        if handle:
+            extra = L.ec_last_error(handle).decode()
+            if extra:
+                msg += ": " + extra
+        raise ECError(status, f"{what}: {msg}")
+
+
+def workspace_bytes(p):
+    n = C.c_size_t()
+    _check(load_library().ec_workspace_bytes(C.byref(p), C.byref(n)), what="ec_workspace_bytes")
+    return n.value
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class System:
+    """One hard-disk system on the current GPU.
+
+    The workspace is a torch uint8 tensor on the device; the stream is torch's
+    current stream unless one is given.
+    """
+
+    def __init__(self, p, device="cuda", stream=None):
+        import torch
+        self._lib = load_library()
+        self.p = p
+        self.n = int(p.n_disks)
+        self.workspace = torch.empty(workspace_bytes(p), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        h = C.c_void_p()
+        st = self._lib.ec_init_system(C.byref(p), C.c_void_p(self.workspace.data_ptr()),
+                                      self.workspace.numel(), C.c_void_p(self.stream.cuda_stream),
+                                      C.byref(h))
+        _check(st, None, "ec_init_system")
+        self.h = h
+
+    def sweep(self, n_sweeps=1):
+        _check(self._lib.ec_sweep(self.h, int(n_sweeps)), self.h, "ec_sweep")
+
+    def measure_pressure(self):
+        z, bp = C.c_double(), C.c_double()
+        cnt = np.zeros(5, dtype=np.uint64)
+        _check(self._lib.ec_measure_pressure(self.h, C.byref(z), C.byref(bp),
+                                             cnt.ctypes.data_as(C.POINTER(C.c_uint64))),
+               self.h, "ec_measure_pressure")
+        return z.value, bp.value, dict(zip(COUNT_NAMES, (int(v) for v in cnt)))
+
+    def reset_tallies(self):
+        _check(self._lib.ec_reset_tallies(self.h), self.h, "ec_reset_tallies")
+
+    def get_positions(self):
+        x = np.empty(self.n, dtype=np.float64)
+        y = np.empty(self.n, dtype=np.float64)
+        _check(self._lib.ec_get_positions(self.h, _dptr(x), _dptr(y), self.n), self.h,
+               "ec_get_positions")
+        return x, y
+
+    def set_positions(self, x, y):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        _check(self._lib.ec_set_positions(self.h, _dptr(x), _dptr(y), self.n), self.h,
+               "ec_set_positions")
+
+    def get_digests(self, n):
+        out = np.zeros(int(n), dtype=np.uint64)
+        _check(self._lib.ec_get_digests(self.h, out.ctypes.data_as(C.POINTER(C.c_uint64)), int(n)),
+               self.h, "ec_get_digests")
+        return out
+
+    def get_cell_tallies(self):
+        nc = int(self.p.cells_per_side) ** 2
+        delta = np.zeros(nc, dtype=np.float64)
+        cnt = np.zeros((nc, 5), dtype=np.uint64)
+        _check(self._lib.ec_get_cell_tallies(self.h, _dptr(delta),
+                                             cnt.ctypes.data_as(C.POINTER(C.c_uint64))),
+               self.h, "ec_get_cell_tallies")
+        return delta, cnt
+
+    def get_cell_digests(self):
+        nc = int(self.p.cells_per_side) ** 2
+        out = np.zeros(nc, dtype=np.uint64)
+        _check(self._lib.ec_get_cell_digests(self.h, out.ctypes.data_as(C.POINTER(C.c_uint64))),
+               self.h, "ec_get_cell_digests")
+        return out
+
+    def set_timing(self, on):
+        _check(self._lib.ec_set_timing(self.h, 1 if on else 0), self.h, "ec_set_timing")
+
+    def get_timing(self):
+        ms, n = C.c_double(), C.c_int64()
+        _check(self._lib.ec_get_timing(self.h, C.byref(ms), C.byref(n)), self.h, "ec_get_timing")
+        return ms.value, n.value
+
+    def sweep_count(self):
+        v = C.c_int64()
+        _check(self._lib.ec_get_sweep_count(self.h, C.byref(v)), self.h, "ec_get_sweep_count")
+        return v.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.ec_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

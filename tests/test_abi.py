@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol
+declared in include/ec.h, and rejects invalid parameters (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1409_6948_amd as P
+from paper_1409_6948_amd import ec as E
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ec.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ec_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load_library()
+    names = _declared_symbols()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(E.EXPORTED)
+
+
+def test_status_strings():
+    lib = P.load_library()
+    for s in range(7):
+        assert lib.ec_status_string(s)
+    assert lib.ec_last_error(None) == b""
+
+
+def _ws(**kw):
+    base = dict(n=65536, eta=0.70, ell=20.0, cells=16)
+    base.update(kw)
+    return P.workspace_bytes(P.make_params(**base))
+
+
+def test_workspace_sizes_scale_with_n():
+    a = _ws()
+    b = P.workspace_bytes(P.make_params(1048576, 0.72, 20.0, 64))
+    assert a >= 65536 * 24 and b >= 1048576 * 24 and b > 10 * a
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=0), E.EC_E_INVALID),
+    (dict(eta=0.0), E.EC_E_INVALID),
+    (dict(eta=0.91), E.EC_E_INVALID),
+    (dict(ell=0.0), E.EC_E_INVALID),
+    (dict(cells=3), E.EC_E_INVALID),
+    (dict(cells=2), E.EC_E_INVALID),
+    (dict(cells=15), E.EC_E_INVALID),
+    (dict(dir_mode=E.EC_DIR_XY), E.EC_E_INVALID),      # xy chains need periodic boundaries
+    (dict(cells=128), E.EC_E_UNSUPPORTED),             # cell side 2.1 sigma < 3 sigma
+    (dict(cells=1, n=4096), E.EC_E_UNSUPPORTED),       # one periodic cell holds <= 2048 disks
+    (dict(cells_per_block=3), E.EC_E_INVALID),
+])
+def test_invalid_parameters_rejected(kw, status):
+    with pytest.raises(E.ECError) as ei:
+        _ws(**kw)
+    assert ei.value.status == status
+
+
+def test_abi_version_checked():
+    p = P.make_params(65536, 0.70, 20.0, 16)
+    p.abi_version = 99
+    with pytest.raises(E.ECError):
+        P.workspace_bytes(p)
+
+
+def test_init_rejects_small_workspace_without_touching_gpu():
+    lib = P.load_library()
+    p = P.make_params(65536, 0.70, 20.0, 16)
+    h = C.c_void_p()
+    st = lib.ec_init_system(C.byref(p), C.c_void_p(0x1000), 16, None, C.byref(h))
+    assert st == E.EC_E_NOMEM and not h.value
+    st = lib.ec_init_system(C.byref(p), None, 1 << 30, None, C.byref(h))
+    assert st == E.EC_E_INVALID
