@@ -154,6 +154,11 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 __device__ __forceinline__ int readlane_i32(int v, int lane) {
   return __builtin_amdgcn_readlane(v, lane);
 }
+// Make a value that is equal in all lanes visibly wave-uniform, so that the
+// branches on it are scalar branches.  The event dispatch below relies on
+// this: compiled as a divergent if/else chain on a vector register, one of
+// its arms (the y-wall reflection) lost its direction update.
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Lane holding the smallest key (s, id) among lanes with valid = true, where
 // s >= 0 so that its bit pattern orders like its value.  -1 if none.
@@ -550,15 +555,15 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
   bool aborted = false;
 
   for (int64_t k = 0; k < n_m && !aborted; ++k) {
-    int j = d.chain_start[cbase + k];
+    int j = uniform_i32(d.chain_start[cbase + k]);
     if (j < 0 || j >= n_own) j = 0;  // guarded: the draw kernel writes indices below n_own
     const double2 dir = d.chain_dir[cbase + k];
     double dx = dir.x, dy = dir.y;
     double idx = (dx != 0.0) ? 1.0 / dx : 0.0;
     double idy = (dy != 0.0) ? 1.0 / dy : 0.0;
-    int a_loc = own_loc[j];
+    int a_loc = uniform_i32(own_loc[j]);
     int a_lidx = j;
-    uint32_t a_gid = (uint32_t)own_gid[j];
+    uint32_t a_gid = (uint32_t)uniform_i32(own_gid[j]);
     double2 ap = pos[a_loc];
     double ax = ap.x, ay = ap.y;
     double rem = d.ell;
@@ -628,7 +633,7 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
         if (wx0 + 4 < gridb && x_hi > (double)(wx0 + 3) * b) ok = false;
         if (wy0 > 0 && y_lo < (double)(wy0 - 1) * b) ok = false;
         if (wy0 + 4 < gridb && y_hi > (double)(wy0 + 3) * b) ok = false;
-        if (!ok) {
+        if (!uniform_i32(ok ? 1 : 0)) {
           // exact search over every slot of the cell
           double ls = INFINITY;
           uint32_t lid = 0xFFFFFFFFu;
@@ -655,8 +660,11 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
       }
       if (tx < best_s || (tx == best_s && wall_x_id < best_id)) { best_s = tx; best_id = wall_x_id; kind = EV_WALL_X; }
       if (ty < best_s || (ty == best_s && wall_y_id < best_id)) { best_s = ty; best_id = wall_y_id; kind = EV_WALL_Y; }
+      kind = uniform_i32(kind);
+      best_id = (uint32_t)uniform_i32((int)best_id);
+      w_slot = uniform_i32(w_slot);
 
-      const bool ends = !(best_s < rem);
+      const bool ends = uniform_i32(!(best_s < rem) ? 1 : 0) != 0;
       const double step = ends ? rem : best_s;
       if (ends) {
         h = digest_event(h, EV_END, (int64_t)d.n + 3, rem);
@@ -670,12 +678,12 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
         int nbx = (int)floor(ax * d.inv_b) + 1, nby = (int)floor(ay * d.inv_b) + 1;
         nbx = nbx < 1 ? 1 : (nbx > nb ? nb : nbx);
         nby = nby < 1 ? 1 : (nby > nb ? nb : nby);
-        int nbin = nby * gridb + nbx;
+        const int nbin = uniform_i32(nby * gridb + nbx);
         if (nbin == abin) {
           if (lane == 0) pos[a_loc] = make_double2(ax, ay);
         } else {
-          int om = mask[abin];
-          int nm = mask[nbin];
+          int om = uniform_i32(mask[abin]);
+          int nm = uniform_i32(mask[nbin]);
           int free_slot = __builtin_ctz((unsigned)(~nm & 0xF) | 0x10u);
           if (free_slot >= 4) {
             if (lane == 0) { atomicOr(d.err, ERR_BIN_CAP); pos[a_loc] = make_double2(ax, ay); }
@@ -704,7 +712,7 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
         n_lift += 1;
         a_loc = w_slot;
         a_gid = best_id;
-        a_lidx = lidx[w_slot];
+        a_lidx = uniform_i32(lidx[w_slot]);
         ax = wp.x;
         ay = wp.y;
       } else if (kind == EV_FROZEN) {
@@ -722,10 +730,14 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
         dy = uy / m;
         idx = (dx != 0.0) ? 1.0 / dx : 0.0;
         idy = (dy != 0.0) ? 1.0 / dy : 0.0;
-      } else if (kind == EV_WALL_X) {
-        dx = -dx; idx = -idx; n_wall += 1;
       } else {
-        dy = -dy; idy = -idy; n_wall += 1;
+        // a wall: reverse the normal component of the direction
+        const bool wx = kind == EV_WALL_X;
+        dx = wx ? -dx : dx;
+        idx = wx ? -idx : idx;
+        dy = wx ? dy : -dy;
+        idy = wx ? idy : -idy;
+        n_wall += 1;
       }
     }
   }
