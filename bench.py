@@ -34,6 +34,24 @@ FLOP_PER_EVENT = 100.0
 HBM_BYTES_PER_DISK = 16 + 8 + 8 + 20 + 16 + 20
 
 
+def measured_traffic(workload):
+    """HBM bytes per phase-kernel launch from the committed counter summary, or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_1409_6948_amd", "csrc", "ec_kernels.hip")
+    prof = os.path.join(ROOT, "profiles", f"k_phase_{workload}_counters.md")
+    if not os.path.exists(prof):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(prof):
+        m = re.match(r"traffic: .*source_sha256_prefix=(\w+) read_bytes_per_launch=(\S+) "
+                     r"write_bytes_per_launch=(\S+)", line)
+        if m and m.group(1) == sha:
+            return float(m.group(2)) + float(m.group(3))
+    return None
+
+
 def cpu_baseline(w, budget_s=15.0):
     """Time the CPU oracle on first-phase cells of sweep 0 from the lattice."""
     from oracle import oracle as O
@@ -64,6 +82,9 @@ def main():
     ap.add_argument("--workload", default="pec_1m")
     ap.add_argument("--cells-per-block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a kernel of "
+                         "known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -78,6 +99,15 @@ def main():
     p = P.make_params(w["n"], w["eta"], w["ell"], w["cells"], dir_mode=w["dir_mode"],
                       seed=w["seed"], cells_per_block=args.cells_per_block)
     g = P.System(p, device="cuda:0")
+    if args.copy_probe_mb > 0:
+        nbytes = args.copy_probe_mb << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy probe: {nbytes} bytes read and written", file=sys.stderr, flush=True)
+        del src, dst
     print(f"# workload {args.workload}: warmup {args.warmup} sweeps", file=sys.stderr, flush=True)
     g.sweep(args.warmup)
     torch.cuda.synchronize()
@@ -131,7 +161,8 @@ def main():
         "wall_s": wall,
         "roofline": {"bound": "alu", "kernel": "k_phase", "achieved": achieved_tf,
                      "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s",
-                     "frac": achieved_tf / FP64_VECTOR_PEAK_TF, "traffic": None,
+                     "frac": achieved_tf / FP64_VECTOR_PEAK_TF,
+                     "traffic": measured_traffic(args.workload),
                      "avg_launch_ms": avg_phase_s * 1e3, "launches": launches,
                      "phase_share_of_sweep": phase_ms / gpu_ms},
     }
