@@ -70,9 +70,10 @@ struct Dev {
   uint32_t system;
 };
 
-// LDS layout of one simulation cell in the walled-cell kernel.
+// LDS layout of one simulation cell in the walled-cell kernel: per slot an
+// FP64 position and a 64-bit word (disk id | frozen bit, local own index).
 struct CellLds {
-  int32_t off_pos, off_gid, off_lidx, off_mask, off_own_gid, off_own_loc, off_tmp, bytes;
+  int32_t off_pos, off_meta, off_mask, off_own_gid, off_own_loc, off_tmp, bytes;
 };
 
 __host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own) {
@@ -80,8 +81,7 @@ __host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own) {
   int slots = gridb * gridb * 4;
   int o = 0;
   l.off_pos = o;      o += 16 * slots;
-  l.off_gid = o;      o += 4 * slots;
-  l.off_lidx = o;     o += 4 * slots;
+  l.off_meta = o;     o += 8 * slots;
   l.off_mask = o;     o += 4 * gridb * gridb;
   l.off_own_gid = o;  o += 4 * cap_own;
   l.off_own_loc = o;  o += 4 * cap_own;

@@ -184,6 +184,43 @@ __device__ __forceinline__ int wave_argmin(double s, uint32_t id, bool valid) {
   return wl;
 }
 
+// Minimum of a 32-bit value over the 64 lanes, left in every lane: DPP steps
+// within rows of 16, then the gfx950 row-pair and half-wave swaps (no trip
+// through a scalar register).
+__device__ __forceinline__ unsigned wave_min_all(unsigned v) {
+  v = umin_(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true));
+  v = umin_(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true));
+  v = umin_(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true));
+  v = umin_(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true));
+  const auto r16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = umin_((unsigned)r16[0], (unsigned)r16[1]);
+  const auto r32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return umin_((unsigned)r32[0], (unsigned)r32[1]);
+}
+
+// As wave_argmin, with the minimum of the high words kept in every lane.
+__device__ __forceinline__ int wave_argmin_all(double s, uint32_t id, bool valid) {
+  const uint64_t sb = (uint64_t)__double_as_longlong(s);
+  const unsigned hi = valid ? (unsigned)(sb >> 32) : 0xFFFFFFFFu;
+  const unsigned m = wave_min_all(hi);
+  uint64_t mask = __ballot(valid && hi == m);
+  if (mask == 0) return -1;
+  int wl = __ffsll((unsigned long long)mask) - 1;
+  mask &= mask - 1;
+  if (mask) {  // equal high words: resolve on the full key
+    uint64_t bs = readlane_u64(sb, wl);
+    uint32_t bi = (uint32_t)readlane_i32((int)id, wl);
+    while (mask) {
+      const int l = __ffsll((unsigned long long)mask) - 1;
+      mask &= mask - 1;
+      const uint64_t ls = readlane_u64(sb, l);
+      const uint32_t li = (uint32_t)readlane_i32((int)id, l);
+      if (ls < bs || (ls == bs && li < bi)) { bs = ls; bi = li; wl = l; }
+    }
+  }
+  return wl;
+}
+
 // Event digest (order-sensitive hash of (kind, id, distance)).
 __device__ __forceinline__ uint64_t digest_event(uint64_t h, int kind, int64_t gid, double s) {
   uint64_t sb = (uint64_t)__double_as_longlong(s);
@@ -459,8 +496,7 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
   const CellLds lay = cell_lds_layout(gridb, d.cap_own);
   unsigned char* base = lds_raw + (size_t)wave * d.lds_per_cell;
   double2* pos = (double2*)(base + lay.off_pos);
-  uint32_t* gid = (uint32_t*)(base + lay.off_gid);
-  int32_t* lidx = (int32_t*)(base + lay.off_lidx);
+  uint64_t* meta = (uint64_t*)(base + lay.off_meta);
   int32_t* mask = (int32_t*)(base + lay.off_mask);
   int32_t* own_gid = (int32_t*)(base + lay.off_own_gid);
   int32_t* own_loc = (int32_t*)(base + lay.off_own_loc);
@@ -499,8 +535,7 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
     if (slot >= 4) { atomicOr(d.err, ERR_BIN_CAP); continue; }
     int s = bin * 4 + slot;
     pos[s] = make_double2(vx, vy);
-    gid[s] = (uint32_t)g;
-    lidx[s] = k;
+    meta[s] = ((uint64_t)(uint32_t)k << 32) | (uint32_t)g;
     own_loc[k] = s;
   }
   // frozen disks: centres of the 8 neighbouring cells within sigma of this cell
@@ -527,8 +562,7 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
         if (slot >= 4) { atomicOr(d.err, ERR_BIN_CAP); continue; }
         int s = bin * 4 + slot;
         pos[s] = make_double2(vx, vy);
-        gid[s] = (uint32_t)g | kFrozenBit;
-        lidx[s] = -1;
+        meta[s] = (0xFFFFFFFFull << 32) | ((uint32_t)g | kFrozenBit);
       }
     }
   }
@@ -544,14 +578,22 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
   const int64_t n_m = chains_of(d, n_own);
   const int64_t cbase = chain_base(d, cell);
   double acc = d.acc_delta[cell];
-  uint64_t n_lift = 0, n_frozen = 0, n_wall = 0;
+  uint32_t n_lift = 0, n_frozen = 0, n_wall = 0;
   uint64_t h = 0;
   const int lx = lane & 3, ly = (lane >> 2) & 3, ks = lane >> 4;
+  const int loff = ((ly * gridb) + lx) * 4 + ks;  // this lane's slot inside a window
+  const double inv_b = d.inv_b;
+  // A window of 4 x 4 bins extends at least 2b ahead of the moving disk's bin
+  // and at least b behind it along each axis (clamped windows only add room,
+  // since nothing is staged beyond the outer bins).  With b >= sigma + eps, a
+  // move of length t keeps its sigma-neighbourhood inside the window whenever
+  // t * max(|dx|, |dy|) <= 2b - sigma - eps: then no disk outside the window
+  // can be hit first, and the event found in the window is exact.
   const double eps = 1e-9 * sigma;
-  const double b = d.b;
-  const uint32_t wall_x_id = (uint32_t)d.n, wall_y_id = (uint32_t)d.n + 1u;
-  const bool use_window = d.search == 0;
-  int64_t since_poll = 0;
+  const double reach = 2.0 * d.b - sigma - eps;
+  const bool use_window = d.search == 0 && d.b >= sigma + eps;
+  const uint64_t wall_x_id = (uint64_t)d.n, wall_y_id = (uint64_t)d.n + 1, end_id = (uint64_t)d.n + 3;
+  int since_poll = 0;
   bool aborted = false;
 
   for (int64_t k = 0; k < n_m && !aborted; ++k) {
@@ -559,18 +601,33 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
     if (j < 0 || j >= n_own) j = 0;  // guarded: the draw kernel writes indices below n_own
     const double2 dir = d.chain_dir[cbase + k];
     double dx = dir.x, dy = dir.y;
-    double idx = (dx != 0.0) ? 1.0 / dx : 0.0;
-    double idy = (dy != 0.0) ? 1.0 / dy : 0.0;
+    // per-direction constants
+    double idx, idy, wallx, wally, idxw, idyw, dsafe;
+    int xneg, yneg;
+#define EC_SET_DIRECTION()                                                          \
+    do {                                                                            \
+      idx = (dx != 0.0) ? 1.0 / dx : 0.0;                                           \
+      idy = (dy != 0.0) ? 1.0 / dy : 0.0;                                           \
+      wallx = (dx > 0.0) ? w : ((dx < 0.0) ? 0.0 : INFINITY);                       \
+      wally = (dy > 0.0) ? w : ((dy < 0.0) ? 0.0 : INFINITY);                       \
+      idxw = (dx != 0.0) ? idx : 1.0;                                               \
+      idyw = (dy != 0.0) ? idy : 1.0;                                               \
+      dsafe = use_window ? reach / fmax(fabs(dx), fabs(dy)) : -1.0;                 \
+      xneg = uniform_i32(dx < 0.0 ? 1 : 0);                                         \
+      yneg = uniform_i32(dy < 0.0 ? 1 : 0);                                         \
+    } while (0)
+    EC_SET_DIRECTION();
     int a_loc = uniform_i32(own_loc[j]);
     int a_lidx = j;
     uint32_t a_gid = (uint32_t)uniform_i32(own_gid[j]);
-    double2 ap = pos[a_loc];
+    int abx = (a_loc >> 2) % gridb, aby = (a_loc >> 2) / gridb;
+    const double2 ap = pos[a_loc];
     double ax = ap.x, ay = ap.y;
     double rem = d.ell;
-    int64_t n_events = 0;
+    int n_events = 0;
 
     for (;;) {
-      if (++n_events > kMaxEventsPerChain) {
+      if (++n_events > (int)kMaxEventsPerChain) {
         if (lane == 0) {
           atomicOr(d.err, ERR_EVENT_CAP);
           if (atomicAdd(d.err + 1, 1) == 0) {
@@ -583,163 +640,178 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
         aborted = true;
         break;
       }
-      if (++since_poll >= kAbortPollEvents) {
+      if (++since_poll >= (int)kAbortPollEvents) {
         since_poll = 0;
         if (load_err(d) != 0) { aborted = true; break; }
       }
-      // -- window search: 4 x 4 bins x 4 slots, one slot per lane
-      const int abin = a_loc >> 2;
-      const int abx = abin % gridb, aby = abin / gridb;
-      int wx0 = abx - (dx < 0.0 ? 2 : 1);
-      int wy0 = aby - (dy < 0.0 ? 2 : 1);
+      // -- window of 4 x 4 bins around the moving disk, one slot per lane
+      int wx0 = abx - 1 - xneg, wy0 = aby - 1 - yneg;
       wx0 = wx0 < 0 ? 0 : (wx0 > gridb - 4 ? gridb - 4 : wx0);
       wy0 = wy0 < 0 ? 0 : (wy0 > gridb - 4 ? gridb - 4 : wy0);
-      int slot = (((wy0 + ly) * gridb) + (wx0 + lx)) * 4 + ks;
-      double2 p = pos[slot];
-      uint32_t g = gid[slot];
-      double s = 0.0;
-      bool valid = contact(p.x - ax, p.y - ay, dx, dy, sig2, s);
-      int wl = wave_argmin(s, g & ~kFrozenBit, valid);
+      const int slot = ((wy0 * gridb) + wx0) * 4 + loff;
+      const double2 p = pos[slot];
+      const uint64_t m = meta[slot];
 
-      // walls of the cell
-      double tx = INFINITY, ty = INFINITY;
-      if (dx != 0.0) { tx = (dx > 0.0) ? (w - ax) * idx : (0.0 - ax) * idx; if (tx < 0.0) tx = 0.0; }
-      if (dy != 0.0) { ty = (dy > 0.0) ? (w - ay) * idy : (0.0 - ay) * idy; if (ty < 0.0) ty = 0.0; }
+      // walls of the cell: (wall - v) / d with 1/d precomputed, clamped at 0
+      double tx = (wallx - ax) * idxw;
+      tx = (tx < 0.0) ? 0.0 : tx;
+      double ty = (wally - ay) * idyw;
+      ty = (ty < 0.0) ? 0.0 : ty;
+
+      double s = 0.0;
+      const bool valid = contact(p.x - ax, p.y - ay, dx, dy, sig2, s);
+      const int wl = wave_argmin_all(s, (uint32_t)m & ~kFrozenBit, valid);
 
       double best_s = INFINITY;
-      uint32_t best_id = 0xFFFFFFFFu;
-      int kind = 0;
-      int w_slot = -1;
-      double2 wp = nan2;
+      uint32_t wgid = 0xFFFFFFFFu;
+      int w_lidx = -1, w_slot = -1, w_bx = 0, w_by = 0;
+      double wpx = 0.0, wpy = 0.0;
       if (wl >= 0) {
         best_s = readlane_f64(s, wl);
-        uint32_t gw = (uint32_t)readlane_i32((int)g, wl);
-        best_id = gw & ~kFrozenBit;
-        kind = (gw & kFrozenBit) ? EV_FROZEN : EV_LIFT;
-        w_slot = readlane_i32(slot, wl);
-        wp.x = readlane_f64(p.x, wl);
-        wp.y = readlane_f64(p.y, wl);
+        const uint64_t mw = readlane_u64(m, wl);
+        wgid = (uint32_t)mw;
+        w_lidx = (int)(uint32_t)(mw >> 32);
+        wpx = readlane_f64(p.x, wl);
+        wpy = readlane_f64(p.y, wl);
+        w_bx = wx0 + (wl & 3);
+        w_by = wy0 + ((wl >> 2) & 3);
+        w_slot = ((w_by * gridb) + w_bx) * 4 + (wl >> 4);
       }
-      // guard: every disk outside the window is farther than the event found
-      {
-        double t = best_s < rem ? best_s : rem;
-        t = t < tx ? t : tx;
-        t = t < ty ? t : ty;
-        double ex = fma(t, dx, ax), ey = fma(t, dy, ay);
-        double x_lo = (ax < ex ? ax : ex) - sigma - eps, x_hi = (ax > ex ? ax : ex) + sigma + eps;
-        double y_lo = (ay < ey ? ay : ey) - sigma - eps, y_hi = (ay > ey ? ay : ey) + sigma + eps;
-        bool ok = use_window;
-        if (wx0 > 0 && x_lo < (double)(wx0 - 1) * b) ok = false;
-        if (wx0 + 4 < gridb && x_hi > (double)(wx0 + 3) * b) ok = false;
-        if (wy0 > 0 && y_lo < (double)(wy0 - 1) * b) ok = false;
-        if (wy0 + 4 < gridb && y_hi > (double)(wy0 + 3) * b) ok = false;
-        if (!uniform_i32(ok ? 1 : 0)) {
-          // exact search over every slot of the cell
-          double ls = INFINITY;
-          uint32_t lid = 0xFFFFFFFFu;
-          int lslot = -1;
-          for (int sl = lane; sl < nslots; sl += 64) {
-            double2 q2 = pos[sl];
-            double s2;
-            if (contact(q2.x - ax, q2.y - ay, dx, dy, sig2, s2)) {
-              uint32_t i2 = gid[sl] & ~kFrozenBit;
-              if (s2 < ls || (s2 == ls && i2 < lid)) { ls = s2; lid = i2; lslot = sl; }
-            }
-          }
-          int fl = wave_argmin(ls, lid, lslot >= 0);
-          best_s = INFINITY; best_id = 0xFFFFFFFFu; kind = 0; w_slot = -1;
-          if (fl >= 0) {
-            best_s = readlane_f64(ls, fl);
-            w_slot = readlane_i32(lslot, fl);
-            uint32_t gw = gid[w_slot];
-            best_id = gw & ~kFrozenBit;
-            kind = (gw & kFrozenBit) ? EV_FROZEN : EV_LIFT;
-            wp = pos[w_slot];
+      // the decision, made in vector registers and moved to the scalar unit once
+      int packed;
+      double e, step, nax, nay;
+#define EC_DECIDE(CHECK_WINDOW)                                                     \
+      do {                                                                          \
+        int kd = (best_s < INFINITY) ? ((wgid & kFrozenBit) ? EV_FROZEN : EV_LIFT) : 0; \
+        e = best_s;                                                                 \
+        if (tx < e) { e = tx; kd = EV_WALL_X; }                                     \
+        if (ty < e) { e = ty; kd = EV_WALL_Y; }                                     \
+        const bool en = !(e < rem);                                                 \
+        step = en ? rem : e;                                                        \
+        nax = fma(step, dx, ax);                                                    \
+        nay = fma(step, dy, ay);                                                    \
+        int bx_ = (int)floor(nax * inv_b) + 1, by_ = (int)floor(nay * inv_b) + 1;   \
+        bx_ = bx_ < 1 ? 1 : (bx_ > nb ? nb : bx_);                                  \
+        by_ = by_ < 1 ? 1 : (by_ > nb ? nb : by_);                                  \
+        bool ok_ = true;                                                            \
+        if (CHECK_WINDOW) {                                                         \
+          const double tmin = fmin(fmin(best_s, rem), fmin(tx, ty));                \
+          ok_ = tmin <= dsafe;                                                      \
+        }                                                                           \
+        packed = uniform_i32(bx_ | (by_ << 8) | (kd << 16) | ((en ? 1 : 0) << 20) | \
+                             ((ok_ ? 1 : 0) << 21));                                \
+      } while (0)
+      EC_DECIDE(true);
+      if (((packed >> 21) & 1) == 0) {
+        // the window cannot vouch for this event: exact search over every slot
+        double ls = INFINITY;
+        uint32_t lid = 0xFFFFFFFFu;
+        int lslot = -1;
+        for (int sl = lane; sl < nslots; sl += 64) {
+          const double2 q2 = pos[sl];
+          double s2;
+          if (contact(q2.x - ax, q2.y - ay, dx, dy, sig2, s2)) {
+            const uint32_t i2 = (uint32_t)meta[sl] & ~kFrozenBit;
+            if (s2 < ls || (s2 == ls && i2 < lid)) { ls = s2; lid = i2; lslot = sl; }
           }
         }
+        const int fl = wave_argmin_all(ls, lid, lslot >= 0);
+        best_s = INFINITY;
+        wgid = 0xFFFFFFFFu;
+        if (fl >= 0) {
+          best_s = readlane_f64(ls, fl);
+          w_slot = readlane_i32(lslot, fl);
+          const uint64_t mw = meta[w_slot];
+          wgid = (uint32_t)uniform_i32((int)(uint32_t)mw);
+          w_lidx = uniform_i32((int)(uint32_t)(mw >> 32));
+          w_bx = (w_slot >> 2) % gridb;
+          w_by = (w_slot >> 2) / gridb;
+          const double2 q2 = pos[w_slot];
+          wpx = q2.x;
+          wpy = q2.y;
+        }
+        EC_DECIDE(false);
       }
-      if (tx < best_s || (tx == best_s && wall_x_id < best_id)) { best_s = tx; best_id = wall_x_id; kind = EV_WALL_X; }
-      if (ty < best_s || (ty == best_s && wall_y_id < best_id)) { best_s = ty; best_id = wall_y_id; kind = EV_WALL_Y; }
-      kind = uniform_i32(kind);
-      best_id = (uint32_t)uniform_i32((int)best_id);
-      w_slot = uniform_i32(w_slot);
-
-      const bool ends = uniform_i32(!(best_s < rem) ? 1 : 0) != 0;
-      const double step = ends ? rem : best_s;
-      if (ends) {
-        h = digest_event(h, EV_END, (int64_t)d.n + 3, rem);
-      } else {
-        h = digest_event(h, kind, (int64_t)best_id, best_s);
+#undef EC_DECIDE
+      const int kind = (packed >> 16) & 7;
+      const bool ends = ((packed >> 20) & 1) != 0;
+      const int nbx = packed & 0xFF, nby = (packed >> 8) & 0xFF;
+      {
+        // event digest (vector unit; nothing on the event path waits for it)
+        const uint64_t eid = ends ? end_id
+                                  : (kind == EV_WALL_X ? wall_x_id
+                                                       : (kind == EV_WALL_Y ? wall_y_id
+                                                                            : (uint64_t)(wgid & ~kFrozenBit)));
+        const uint64_t ek = (uint64_t)(ends ? EV_END : kind);
+        const uint64_t ev = (uint64_t)__double_as_longlong(step) ^ (eid * 0x9E3779B97F4A7C15ull) ^ (ek << 56);
+        h = (h ^ ev) * 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 31;
       }
-      ax = fma(step, dx, ax);
-      ay = fma(step, dy, ay);
+      ax = nax;
+      ay = nay;
       // store the moved disk; move it to another bin if it crossed a bin edge
-      {
-        int nbx = (int)floor(ax * d.inv_b) + 1, nby = (int)floor(ay * d.inv_b) + 1;
-        nbx = nbx < 1 ? 1 : (nbx > nb ? nb : nbx);
-        nby = nby < 1 ? 1 : (nby > nb ? nb : nby);
-        const int nbin = uniform_i32(nby * gridb + nbx);
-        if (nbin == abin) {
-          if (lane == 0) pos[a_loc] = make_double2(ax, ay);
+      if (nbx == abx && nby == aby) {
+        if (lane == 0) pos[a_loc] = make_double2(ax, ay);
+      } else {
+        const int abin = aby * gridb + abx, nbin = nby * gridb + nbx;
+        const int nm = uniform_i32(mask[nbin]);
+        const int free_slot = __builtin_ctz((unsigned)(~nm & 0xF) | 0x10u);
+        if (free_slot >= 4) {
+          if (lane == 0) { atomicOr(d.err, ERR_BIN_CAP); pos[a_loc] = make_double2(ax, ay); }
         } else {
-          int om = uniform_i32(mask[abin]);
-          int nm = uniform_i32(mask[nbin]);
-          int free_slot = __builtin_ctz((unsigned)(~nm & 0xF) | 0x10u);
-          if (free_slot >= 4) {
-            if (lane == 0) { atomicOr(d.err, ERR_BIN_CAP); pos[a_loc] = make_double2(ax, ay); }
-          } else {
-            int ns = nbin * 4 + free_slot;
-            if (lane == 0) {
-              mask[abin] = om & ~(1 << (a_loc & 3));
-              pos[a_loc] = nan2;
-              mask[nbin] = nm | (1 << free_slot);
-              pos[ns] = make_double2(ax, ay);
-              gid[ns] = a_gid;
-              lidx[ns] = a_lidx;
-              own_loc[a_lidx] = ns;
-            }
-            a_loc = ns;
+          const int ns = nbin * 4 + free_slot;
+          if (lane == 0) {
+            mask[abin] = mask[abin] & ~(1 << (a_loc & 3));
+            pos[a_loc] = nan2;
+            mask[nbin] = nm | (1 << free_slot);
+            pos[ns] = make_double2(ax, ay);
+            meta[ns] = ((uint64_t)(uint32_t)a_lidx << 32) | a_gid;
+            own_loc[a_lidx] = ns;
           }
+          a_loc = ns;
+          abx = nbx;
+          aby = nby;
         }
-        wave_sync();
       }
+      wave_sync();
       if (ends) break;
-      rem = rem - best_s;
+      rem = rem - e;
       if (kind == EV_LIFT) {
         // straight chain: the hit disk goes on in the same direction
-        double rx = wp.x - ax, ry = wp.y - ay;
-        acc = acc + fma(rx, dx, ry * dy);
+        acc = acc + fma(wpx - ax, dx, (wpy - ay) * dy);
         n_lift += 1;
         a_loc = w_slot;
-        a_gid = best_id;
-        a_lidx = uniform_i32(lidx[w_slot]);
-        ax = wp.x;
-        ay = wp.y;
+        a_gid = wgid;
+        a_lidx = w_lidx;
+        abx = w_bx;
+        aby = w_by;
+        ax = wpx;
+        ay = wpy;
       } else if (kind == EV_FROZEN) {
         // mirror the direction about the contact normal
-        double rx = wp.x - ax, ry = wp.y - ay;
+        const double rx = wpx - ax, ry = wpy - ay;
         acc = acc + fma(rx, dx, ry * dy);
         n_frozen += 1;
-        double nrm = sqrt(fma(rx, rx, ry * ry));
-        double nx = rx / nrm, ny = ry / nrm;
-        double dn = fma(dx, nx, dy * ny);
-        double tt = -2.0 * dn;
-        double ux = fma(tt, nx, dx), uy = fma(tt, ny, dy);
-        double m = sqrt(fma(ux, ux, uy * uy));
-        dx = ux / m;
-        dy = uy / m;
-        idx = (dx != 0.0) ? 1.0 / dx : 0.0;
-        idy = (dy != 0.0) ? 1.0 / dy : 0.0;
+        const double nrm = sqrt(fma(rx, rx, ry * ry));
+        const double nx = rx / nrm, ny = ry / nrm;
+        const double dn = fma(dx, nx, dy * ny);
+        const double tt = -2.0 * dn;
+        const double ux = fma(tt, nx, dx), uy = fma(tt, ny, dy);
+        const double mm = sqrt(fma(ux, ux, uy * uy));
+        dx = ux / mm;
+        dy = uy / mm;
+        EC_SET_DIRECTION();
       } else {
         // a wall: reverse the normal component of the direction
-        const bool wx = kind == EV_WALL_X;
-        dx = wx ? -dx : dx;
-        idx = wx ? -idx : idx;
-        dy = wx ? dy : -dy;
-        idy = wx ? idy : -idy;
         n_wall += 1;
+        if (kind == EV_WALL_X) {
+          dx = -dx; idx = -idx; idxw = -idxw; wallx = w - wallx; xneg ^= 1;
+        } else {
+          dy = -dy; idy = -idy; idyw = -idyw; wally = w - wally; yneg ^= 1;
+        }
       }
     }
+#undef EC_SET_DIRECTION
   }
 
   // ---- write back: old position + local displacement, wrapped --------------
