@@ -593,10 +593,10 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
   const double reach = 2.0 * d.b - sigma - eps;
   const bool use_window = d.search == 0 && d.b >= sigma + eps;
   const uint64_t wall_x_id = (uint64_t)d.n, wall_y_id = (uint64_t)d.n + 1, end_id = (uint64_t)d.n + 3;
-  int since_poll = 0;
-  bool aborted = false;
+  int aborted = 0;
+  int stop = 0;  // nonzero once a poll sees the device error word set
 
-  for (int64_t k = 0; k < n_m && !aborted; ++k) {
+  for (int64_t k = 0; k < n_m && aborted == 0; ++k) {
     int j = uniform_i32(d.chain_start[cbase + k]);
     if (j < 0 || j >= n_own) j = 0;  // guarded: the draw kernel writes indices below n_own
     const double2 dir = d.chain_dir[cbase + k];
@@ -616,6 +616,16 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
       xneg = uniform_i32(dx < 0.0 ? 1 : 0);                                         \
       yneg = uniform_i32(dy < 0.0 ? 1 : 0);                                         \
     } while (0)
+    // origin bin of the 4 x 4-bin window around bin (bx, by): one bin behind
+    // the disk and two ahead of it along each axis, clamped to the grid
+#define EC_WINDOW(bx, by, xn, yn)                                                   \
+    do {                                                                            \
+      wx0 = (bx) - 1 - (xn);                                                        \
+      wy0 = (by) - 1 - (yn);                                                        \
+      wx0 = wx0 < 0 ? 0 : (wx0 > gridb - 4 ? gridb - 4 : wx0);                      \
+      wy0 = wy0 < 0 ? 0 : (wy0 > gridb - 4 ? gridb - 4 : wy0);                      \
+      wbase = (wy0 * gridb + wx0) * 4;                                              \
+    } while (0)
     EC_SET_DIRECTION();
     int a_loc = uniform_i32(own_loc[j]);
     int a_lidx = j;
@@ -625,58 +635,38 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
     double ax = ap.x, ay = ap.y;
     double rem = d.ell;
     int n_events = 0;
+    int wx0, wy0, wbase;
+    EC_WINDOW(abx, aby, xneg, yneg);
+    double2 p = pos[wbase + loff];
+    uint64_t m = meta[wbase + loff];
+    int ended = 0;  // the chain length is used up
+    stop = uniform_i32(load_err(d));
 
-    for (;;) {
-      if (++n_events > (int)kMaxEventsPerChain) {
-        if (lane == 0) {
-          atomicOr(d.err, ERR_EVENT_CAP);
-          if (atomicAdd(d.err + 1, 1) == 0) {
-            double* g = d.dbg;
-            g[0] = (double)cell; g[1] = (double)k; g[2] = (double)sweep; g[3] = (double)q;
-            g[4] = ax; g[5] = ay; g[6] = dx; g[7] = dy; g[8] = rem; g[9] = (double)a_loc;
-            g[10] = (double)a_gid; g[11] = (double)n_own;
-          }
-        }
-        aborted = true;
-        break;
-      }
-      if (++since_poll >= (int)kAbortPollEvents) {
-        since_poll = 0;
-        if (load_err(d) != 0) { aborted = true; break; }
-      }
-      // -- window of 4 x 4 bins around the moving disk, one slot per lane
-      int wx0 = abx - 1 - xneg, wy0 = aby - 1 - yneg;
-      wx0 = wx0 < 0 ? 0 : (wx0 > gridb - 4 ? gridb - 4 : wx0);
-      wy0 = wy0 < 0 ? 0 : (wy0 > gridb - 4 ? gridb - 4 : wy0);
-      const int slot = ((wy0 * gridb) + wx0) * 4 + loff;
-      const double2 p = pos[slot];
-      const uint64_t m = meta[slot];
-
+    while (ended == 0 && stop == 0 && n_events < (int)kMaxEventsPerChain) {
       // walls of the cell: (wall - v) / d with 1/d precomputed, clamped at 0
       double tx = (wallx - ax) * idxw;
       tx = (tx < 0.0) ? 0.0 : tx;
       double ty = (wally - ay) * idyw;
       ty = (ty < 0.0) ? 0.0 : ty;
 
+      // -- contact distance of the disk in this lane's window slot
       double s = 0.0;
       const bool valid = contact(p.x - ax, p.y - ay, dx, dy, sig2, s);
       const int wl = wave_argmin_all(s, (uint32_t)m & ~kFrozenBit, valid);
 
-      double best_s = INFINITY;
-      uint32_t wgid = 0xFFFFFFFFu;
-      int w_lidx = -1, w_slot = -1, w_bx = 0, w_by = 0;
-      double wpx = 0.0, wpy = 0.0;
-      if (wl >= 0) {
-        best_s = readlane_f64(s, wl);
-        const uint64_t mw = readlane_u64(m, wl);
-        wgid = (uint32_t)mw;
-        w_lidx = (int)(uint32_t)(mw >> 32);
-        wpx = readlane_f64(p.x, wl);
-        wpy = readlane_f64(p.y, wl);
-        w_bx = wx0 + (wl & 3);
-        w_by = wy0 + ((wl >> 2) & 3);
-        w_slot = ((w_by * gridb) + w_bx) * 4 + (wl >> 4);
-      }
+      // the nearest disk (read from lane 0 when there is none; it is then unused)
+      const int wls = wl < 0 ? 0 : wl;
+      double best_s = readlane_f64(s, wls);
+      const uint64_t mw = readlane_u64(m, wls);
+      uint32_t wgid = (uint32_t)mw;
+      int w_lidx = (int)(uint32_t)(mw >> 32);
+      double wpx = readlane_f64(p.x, wls);
+      double wpy = readlane_f64(p.y, wls);
+      if (wl < 0) { best_s = INFINITY; wgid = 0xFFFFFFFFu; }
+      int w_bx = wx0 + (wls & 3);
+      int w_by = wy0 + ((wls >> 2) & 3);
+      int w_slot = ((w_by * gridb) + w_bx) * 4 + (wls >> 4);
+
       // the decision, made in vector registers and moved to the scalar unit once
       int packed;
       double e, step, nax, nay;
@@ -690,14 +680,11 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
         step = en ? rem : e;                                                        \
         nax = fma(step, dx, ax);                                                    \
         nay = fma(step, dy, ay);                                                    \
-        int bx_ = (int)floor(nax * inv_b) + 1, by_ = (int)floor(nay * inv_b) + 1;   \
-        bx_ = bx_ < 1 ? 1 : (bx_ > nb ? nb : bx_);                                  \
-        by_ = by_ < 1 ? 1 : (by_ > nb ? nb : by_);                                  \
+        /* truncation equals floor for x >= 0; below 0 both clamp to bin 1 */      \
+        const int bx_ = min(max((int)(nax * inv_b) + 1, 1), nb);                    \
+        const int by_ = min(max((int)(nay * inv_b) + 1, 1), nb);                    \
         bool ok_ = true;                                                            \
-        if (CHECK_WINDOW) {                                                         \
-          const double tmin = fmin(fmin(best_s, rem), fmin(tx, ty));                \
-          ok_ = tmin <= dsafe;                                                      \
-        }                                                                           \
+        if (CHECK_WINDOW) ok_ = step <= dsafe;                                      \
         packed = uniform_i32(bx_ | (by_ << 8) | (kd << 16) | ((en ? 1 : 0) << 20) | \
                              ((ok_ ? 1 : 0) << 21));                                \
       } while (0)
@@ -721,14 +708,16 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
         if (fl >= 0) {
           best_s = readlane_f64(ls, fl);
           w_slot = readlane_i32(lslot, fl);
-          const uint64_t mw = meta[w_slot];
-          wgid = (uint32_t)uniform_i32((int)(uint32_t)mw);
-          w_lidx = uniform_i32((int)(uint32_t)(mw >> 32));
+          const uint64_t mw2 = meta[w_slot];
+          wgid = (uint32_t)uniform_i32((int)(uint32_t)mw2);
+          w_lidx = uniform_i32((int)(uint32_t)(mw2 >> 32));
           w_bx = (w_slot >> 2) % gridb;
           w_by = (w_slot >> 2) / gridb;
+          // read into scalar registers here, so no load is left in flight
+          // where this rare path rejoins the event path
           const double2 q2 = pos[w_slot];
-          wpx = q2.x;
-          wpy = q2.y;
+          wpx = readlane_f64(q2.x, 0);
+          wpy = readlane_f64(q2.y, 0);
         }
         EC_DECIDE(false);
       }
@@ -736,17 +725,6 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
       const int kind = (packed >> 16) & 7;
       const bool ends = ((packed >> 20) & 1) != 0;
       const int nbx = packed & 0xFF, nby = (packed >> 8) & 0xFF;
-      {
-        // event digest (vector unit; nothing on the event path waits for it)
-        const uint64_t eid = ends ? end_id
-                                  : (kind == EV_WALL_X ? wall_x_id
-                                                       : (kind == EV_WALL_Y ? wall_y_id
-                                                                            : (uint64_t)(wgid & ~kFrozenBit)));
-        const uint64_t ek = (uint64_t)(ends ? EV_END : kind);
-        const uint64_t ev = (uint64_t)__double_as_longlong(step) ^ (eid * 0x9E3779B97F4A7C15ull) ^ (ek << 56);
-        h = (h ^ ev) * 0xBF58476D1CE4E5B9ull;
-        h ^= h >> 31;
-      }
       ax = nax;
       ay = nay;
       // store the moved disk; move it to another bin if it crossed a bin edge
@@ -773,13 +751,23 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
           aby = nby;
         }
       }
-      wave_sync();
-      if (ends) break;
-      rem = rem - e;
-      if (kind == EV_LIFT) {
+      __builtin_amdgcn_wave_barrier();
+      {
+        // event digest
+        const uint64_t eid = ends ? end_id
+                                  : (kind == EV_WALL_X ? wall_x_id
+                                                       : (kind == EV_WALL_Y ? wall_y_id
+                                                                            : (uint64_t)(wgid & ~kFrozenBit)));
+        const uint64_t ek = (uint64_t)(ends ? EV_END : kind);
+        const uint64_t ev = (uint64_t)__double_as_longlong(step) ^ (eid * 0x9E3779B97F4A7C15ull) ^ (ek << 56);
+        h = (h ^ ev) * 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 31;
+      }
+      if (!ends && kind == EV_LIFT) {
         // straight chain: the hit disk goes on in the same direction
         acc = acc + fma(wpx - ax, dx, (wpy - ay) * dy);
         n_lift += 1;
+        rem = rem - e;
         a_loc = w_slot;
         a_gid = wgid;
         a_lidx = w_lidx;
@@ -787,30 +775,57 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
         aby = w_by;
         ax = wpx;
         ay = wpy;
-      } else if (kind == EV_FROZEN) {
-        // mirror the direction about the contact normal
-        const double rx = wpx - ax, ry = wpy - ay;
-        acc = acc + fma(rx, dx, ry * dy);
-        n_frozen += 1;
-        const double nrm = sqrt(fma(rx, rx, ry * ry));
-        const double nx = rx / nrm, ny = ry / nrm;
-        const double dn = fma(dx, nx, dy * ny);
-        const double tt = -2.0 * dn;
-        const double ux = fma(tt, nx, dx), uy = fma(tt, ny, dy);
-        const double mm = sqrt(fma(ux, ux, uy * uy));
-        dx = ux / mm;
-        dy = uy / mm;
-        EC_SET_DIRECTION();
+      } else if (ends) {
+        ended = 1;
       } else {
-        // a wall: reverse the normal component of the direction
-        n_wall += 1;
-        if (kind == EV_WALL_X) {
-          dx = -dx; idx = -idx; idxw = -idxw; wallx = w - wallx; xneg ^= 1;
+        rem = rem - e;
+        if (kind == EV_FROZEN) {
+          // mirror the direction about the contact normal
+          const double rx = wpx - ax, ry = wpy - ay;
+          acc = acc + fma(rx, dx, ry * dy);
+          n_frozen += 1;
+          const double nrm = sqrt(fma(rx, rx, ry * ry));
+          const double nx = rx / nrm, ny = ry / nrm;
+          const double dn = fma(dx, nx, dy * ny);
+          const double tt = -2.0 * dn;
+          const double ux = fma(tt, nx, dx), uy = fma(tt, ny, dy);
+          const double mm = sqrt(fma(ux, ux, uy * uy));
+          dx = ux / mm;
+          dy = uy / mm;
+          EC_SET_DIRECTION();
         } else {
-          dy = -dy; idy = -idy; idyw = -idyw; wally = w - wally; yneg ^= 1;
+          // a wall: reverse the normal component of the direction
+          n_wall += 1;
+          if (kind == EV_WALL_X) {
+            dx = -dx; idx = -idx; idxw = -idxw; wallx = w - wallx; xneg ^= 1;
+          } else {
+            dy = -dy; idy = -idy; idyw = -idyw; wally = w - wally; yneg ^= 1;
+          }
         }
       }
+      // window of the next event (the stores above are seen: LDS operations
+      // of one wave complete in order)
+      EC_WINDOW(abx, aby, xneg, yneg);
+      p = pos[wbase + loff];
+      m = meta[wbase + loff];
+      // event cap and abort polling (every value here is wave-uniform)
+      ++n_events;
+      if ((n_events & ((int)kAbortPollEvents - 1)) == 0) stop = uniform_i32(load_err(d));
     }
+    if (ended == 0) {
+      // stopped by another wave's error, or this chain reached the event cap
+      if (stop == 0 && lane == 0) {
+        atomicOr(d.err, ERR_EVENT_CAP);
+        if (atomicAdd(d.err + 1, 1) == 0) {
+          double* g = d.dbg;
+          g[0] = (double)cell; g[1] = (double)k; g[2] = (double)sweep; g[3] = (double)q;
+          g[4] = ax; g[5] = ay; g[6] = dx; g[7] = dy; g[8] = rem; g[9] = (double)a_loc;
+          g[10] = (double)a_gid; g[11] = (double)n_own;
+        }
+      }
+      aborted = 1;
+    }
+#undef EC_WINDOW
 #undef EC_SET_DIRECTION
   }
 
