@@ -208,13 +208,18 @@ void orc_set_log(orc_event* buf, int64_t capacity) {
 }
 int64_t orc_log_count(void) { return g_log_n; }
 
-static uint64_t digest_event(uint64_t h, int kind, int64_t gid, double s) {
-  uint64_t sb;
-  memcpy(&sb, &s, sizeof sb);
-  uint64_t e = sb ^ ((uint64_t)gid * 0x9E3779B97F4A7C15ULL) ^ ((uint64_t)kind << 56);
-  h = (h ^ e) * 0xBF58476D1CE4E5B9ULL;
-  h ^= h >> 31;
-  return h;
+/* Event digest (a test device, not part of the method): every event of a
+ * cell's phase gets the record r = bits(s) ^ id*K1 ^ kind<<56, and the cell
+ * digest is the XOR over its events i = 0, 1, ... of mix(r ^ i*K2), with mix
+ * the splitmix64 finaliser (Steele, Lea, Flood, OOPSLA 2014).  The index makes
+ * it order-sensitive; the XOR lets a device hash a batch of events at once. */
+#define DIGEST_K1 0x9E3779B97F4A7C15ULL
+#define DIGEST_K2 0xD6E8FEB86659FD93ULL
+
+static uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -234,7 +239,16 @@ typedef struct {
   double* acc_delta;      /* this cell's accumulators */
   uint64_t* acc_cnt;
   uint64_t digest;
+  uint64_t n_events;       /* events of this cell so far in the phase (digest index) */
 } chain_ctx;
+
+static void digest_event(chain_ctx* cx, int kind, int64_t gid, double s) {
+  uint64_t sb;
+  memcpy(&sb, &s, sizeof sb);
+  const uint64_t r = sb ^ ((uint64_t)gid * DIGEST_K1) ^ ((uint64_t)kind << 56);
+  cx->digest ^= mix64(r ^ (cx->n_events * DIGEST_K2));
+  cx->n_events += 1;
+}
 
 static double min_image(double r, const chain_ctx* cx) {
   if (r < -cx->half_L) r += cx->L;
@@ -318,7 +332,7 @@ static void run_chain(chain_ctx* cx, int64_t a, double dx, double dy, double ell
       /* periodic box: nearest images are exact only for flights up to L/2 - sigma */
       double lim = best_s < rem ? best_s : rem;
       if (lim > cx->cap) {
-        cx->digest = digest_event(cx->digest, ORC_EV_PSEUDO, cx->n + 2, cx->cap);
+        digest_event(cx, ORC_EV_PSEUDO, cx->n + 2, cx->cap);
         move_by(cx, a, cx->cap, dx, dy);
         log_event(cx, ORC_EV_PSEUDO, cx->n + 2, cx->ogid[a], cx->cap, dx, dy, cx->ox[a], cx->oy[a],
                   NAN, NAN);
@@ -329,13 +343,13 @@ static void run_chain(chain_ctx* cx, int64_t a, double dx, double dy, double ell
     }
     if (!(best_s < rem)) {
       /* no event before the displacement is used up: the chain ends */
-      cx->digest = digest_event(cx->digest, ORC_EV_END, cx->n + 3, rem);
+      digest_event(cx, ORC_EV_END, cx->n + 3, rem);
       move_by(cx, a, rem, dx, dy);
       log_event(cx, ORC_EV_END, cx->n + 3, cx->ogid[a], rem, dx, dy, cx->ox[a], cx->oy[a], NAN,
                 NAN);
       break;
     }
-    cx->digest = digest_event(cx->digest, best_kind, best_gid, best_s);
+    digest_event(cx, best_kind, best_gid, best_s);
     move_by(cx, a, best_s, dx, dy);
     rem = rem - best_s;
     ax = cx->ox[a]; ay = cx->oy[a];
@@ -436,6 +450,7 @@ static void sweep_periodic(const orc_params* p, double* x, double* y, int64_t sw
   cx.acc_delta = &acc_delta[0];
   cx.acc_cnt = &acc_cnt[0];
   cx.digest = 0;
+  cx.n_events = 0;
   int64_t n_m = p->chains_per_cell > 0 ? p->chains_per_cell : p->n;
   int64_t* starts = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_m > 0 ? n_m : 1));
   make_start_list(p, sweep, 0, p->n, n_m, starts);
@@ -535,6 +550,7 @@ static void run_cell(const orc_params* p, double* x, double* y, int64_t sweep, i
   cx.acc_delta = &acc_delta[cell];
   cx.acc_cnt = &acc_cnt[(int64_t)cell * ORC_CNT_NCOL];
   cx.digest = 0;
+  cx.n_events = 0;
 
   int64_t n_m = 0;
   if (n_c > 0) n_m = p->chains_per_cell > 0 ? p->chains_per_cell : n_c;

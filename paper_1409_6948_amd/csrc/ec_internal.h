@@ -38,6 +38,8 @@ constexpr int kMaxDrawTries = 256;
 constexpr int kDebugWords = 16;
 
 constexpr int kDigestRing = 1024;
+// Events hashed together, one per lane, by the walled-cell kernel's digest.
+constexpr int kDigestBatch = 64;
 
 // Everything a kernel needs: device pointers into the caller's workspace and
 // the derived constants.  Passed by value.
@@ -71,9 +73,10 @@ struct Dev {
 };
 
 // LDS layout of one simulation cell in the walled-cell kernel: per slot an
-// FP64 position and a 64-bit word (disk id | frozen bit, local own index).
+// FP64 position and a 64-bit word (disk id | frozen bit, local own index);
+// then the own-disk tables and a ring of event records for the digest.
 struct CellLds {
-  int32_t off_pos, off_meta, off_mask, off_own_gid, off_own_loc, off_tmp, bytes;
+  int32_t off_pos, off_meta, off_mask, off_own_gid, off_own_loc, off_tmp, off_ring, bytes;
 };
 
 __host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own) {
@@ -86,6 +89,8 @@ __host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own) {
   l.off_own_gid = o;  o += 4 * cap_own;
   l.off_own_loc = o;  o += 4 * cap_own;
   l.off_tmp = o;      o += 4 * cap_own;
+  o = (o + 15) & ~15;
+  l.off_ring = o;     o += 16 * kDigestBatch;
   l.bytes = (o + 15) & ~15;
   return l;
 }

@@ -221,13 +221,48 @@ __device__ __forceinline__ int wave_argmin_all(double s, uint32_t id, bool valid
   return wl;
 }
 
-// Event digest (order-sensitive hash of (kind, id, distance)).
-__device__ __forceinline__ uint64_t digest_event(uint64_t h, int kind, int64_t gid, double s) {
-  uint64_t sb = (uint64_t)__double_as_longlong(s);
-  uint64_t e = sb ^ ((uint64_t)gid * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)kind << 56);
-  h = (h ^ e) * 0xBF58476D1CE4E5B9ull;
-  h ^= h >> 31;
-  return h;
+// Event digest (a test device, not part of the method).  Event i of a cell's
+// phase has the record r = bits(s) ^ id*K1 ^ kind<<56; the cell digest is the
+// XOR over i of mix(r ^ i*K2), mix being the splitmix64 finaliser (Steele,
+// Lea, Flood, OOPSLA 2014).  The XOR lets a wave hash 64 events at once.
+constexpr uint64_t kDigestK1 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kDigestK2 = 0xD6E8FEB86659FD93ull;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t digest_term(int kind, uint64_t gid, double s, uint64_t i) {
+  const uint64_t r = (uint64_t)__double_as_longlong(s) ^ (gid * kDigestK1) ^ ((uint64_t)kind << 56);
+  return mix64(r ^ (i * kDigestK2));
+}
+
+// XOR of a 32-bit value over the 64 lanes, left in every lane.
+__device__ __forceinline__ unsigned wave_xor_all(unsigned v) {
+  v ^= (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);
+  v ^= (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);
+  v ^= (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true);
+  v ^= (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true);
+  const auto r16 = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = (unsigned)r16[0] ^ (unsigned)r16[1];
+  const auto r32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return (unsigned)r32[0] ^ (unsigned)r32[1];
+}
+
+// Digest terms of the first `count` records of a ring (record k is event
+// first + k: x = bits(s), y = kind << 32 | id), XOR-ed over the wave.
+__device__ __forceinline__ uint64_t digest_batch(const ulonglong2* ring, int lane, int count,
+                                                 uint64_t first) {
+  uint64_t t = 0;
+  if (lane < count) {
+    const ulonglong2 r = ring[lane];
+    t = digest_term((int)(r.y >> 32), r.y & 0xFFFFFFFFull, __longlong_as_double((long long)r.x),
+                    first + (uint64_t)lane);
+  }
+  const uint32_t lo = (uint32_t)uniform_i32((int)wave_xor_all((uint32_t)t));
+  const uint32_t hi = (uint32_t)uniform_i32((int)wave_xor_all((uint32_t)(t >> 32)));
+  return ((uint64_t)hi << 32) | lo;
 }
 
 enum { EV_LIFT = 1, EV_FROZEN = 2, EV_WALL_X = 3, EV_WALL_Y = 4, EV_PSEUDO = 5, EV_END = 6 };
@@ -501,6 +536,7 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
   int32_t* own_gid = (int32_t*)(base + lay.off_own_gid);
   int32_t* own_loc = (int32_t*)(base + lay.off_own_loc);
   int32_t* tmp = (int32_t*)(base + lay.off_tmp);
+  ulonglong2* ring = (ulonglong2*)(base + lay.off_ring);
 
   // ---- stage: own disks, sorted by id -----------------------------------
   const int start = d.cell_start[cell];
@@ -580,6 +616,8 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
   double acc = d.acc_delta[cell];
   uint32_t n_lift = 0, n_frozen = 0, n_wall = 0;
   uint64_t h = 0;
+  int n_ring = 0;          // event records waiting in the ring
+  uint64_t ring_first = 0;  // digest index of the ring's first record
   const int lx = lane & 3, ly = (lane >> 2) & 3, ks = lane >> 4;
   const int loff = ((ly * gridb) + lx) * 4 + ks;  // this lane's slot inside a window
   const double inv_b = d.inv_b;
@@ -727,6 +765,14 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
       const int nbx = packed & 0xFF, nby = (packed >> 8) & 0xFF;
       ax = nax;
       ay = nay;
+      // event record for the digest: bits of the step, kind << 32 | id
+      const uint32_t eid = ends ? (uint32_t)end_id
+                                : (kind == EV_WALL_X ? (uint32_t)wall_x_id
+                                                     : (kind == EV_WALL_Y ? (uint32_t)wall_y_id
+                                                                          : (wgid & ~kFrozenBit)));
+      const uint64_t rtag = ((uint64_t)(ends ? EV_END : kind) << 32) | eid;
+      const ulonglong2 rec = make_ulonglong2((unsigned long long)__double_as_longlong(step), rtag);
+      if (lane == 0) ring[n_ring] = rec;
       // store the moved disk; move it to another bin if it crossed a bin edge
       if (nbx == abx && nby == aby) {
         if (lane == 0) pos[a_loc] = make_double2(ax, ay);
@@ -752,16 +798,10 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
         }
       }
       __builtin_amdgcn_wave_barrier();
-      {
-        // event digest
-        const uint64_t eid = ends ? end_id
-                                  : (kind == EV_WALL_X ? wall_x_id
-                                                       : (kind == EV_WALL_Y ? wall_y_id
-                                                                            : (uint64_t)(wgid & ~kFrozenBit)));
-        const uint64_t ek = (uint64_t)(ends ? EV_END : kind);
-        const uint64_t ev = (uint64_t)__double_as_longlong(step) ^ (eid * 0x9E3779B97F4A7C15ull) ^ (ek << 56);
-        h = (h ^ ev) * 0xBF58476D1CE4E5B9ull;
-        h ^= h >> 31;
+      if (++n_ring == kDigestBatch) {
+        h ^= digest_batch(ring, lane, kDigestBatch, ring_first);
+        ring_first += kDigestBatch;
+        n_ring = 0;
       }
       if (!ends && kind == EV_LIFT) {
         // straight chain: the hit disk goes on in the same direction
@@ -831,6 +871,7 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
 
   // ---- write back: old position + local displacement, wrapped --------------
   wave_sync();
+  h ^= digest_batch(ring, lane, n_ring, ring_first);
   for (int k = lane; k < n_own; k += 64) {
     int g = own_gid[k];
     double2 v = pos[own_loc[k]];
@@ -883,7 +924,7 @@ __global__ void __launch_bounds__(64) k_periodic(Dev d, int64_t sweep) {
   }
   wave_sync();
   double acc = d.acc_delta[0];
-  uint64_t n_lift = 0, n_pseudo = 0, h = 0;
+  uint64_t n_lift = 0, n_pseudo = 0, h = 0, n_ev = 0;
 
   for (int64_t k = 0; k < n_m; ++k) {
     int a;
@@ -924,13 +965,13 @@ __global__ void __launch_bounds__(64) k_periodic(Dev d, int64_t sweep) {
       int kind;
       if (lim > cap) {
         step = cap; kind = EV_PSEUDO;
-        h = digest_event(h, EV_PSEUDO, d.n + 2, cap);
+        h ^= digest_term(EV_PSEUDO, (uint64_t)d.n + 2, cap, n_ev++);
       } else if (!(best_s < rem)) {
         step = rem; kind = EV_END;
-        h = digest_event(h, EV_END, d.n + 3, rem);
+        h ^= digest_term(EV_END, (uint64_t)d.n + 3, rem, n_ev++);
       } else {
         step = best_s; kind = EV_LIFT;
-        h = digest_event(h, EV_LIFT, (int64_t)bj, best_s);
+        h ^= digest_term(EV_LIFT, (uint64_t)bj, best_s, n_ev++);
       }
       ax = fma(step, dx, ax);
       ay = fma(step, dy, ay);
