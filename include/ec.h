@@ -82,7 +82,8 @@ typedef enum {
 typedef struct {
   uint32_t abi_version;     /* must equal EC_ABI_VERSION                                    */
   uint32_t flags;           /* EC_FLAG_* bits, 0 = default                                  */
-  int64_t  n_disks;         /* N; the lattice start needs N = k*k with k even               */
+  int64_t  n_disks;         /* N; the lattice start needs N = k*k with k even; walled cells
+                               (C > 1) take N <= 2^29 - 4 (EC_E_UNSUPPORTED above)       */
   double   sigma;           /* disk diameter, > 0                                           */
   double   eta;             /* 0 < eta < pi/(2 sqrt 3); L = sigma sqrt(N pi / (4 eta))       */
   double   ell;             /* displacement of one chain, > 0                               */

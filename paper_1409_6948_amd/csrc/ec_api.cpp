@@ -97,6 +97,9 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
     if (!(w > p->sigma)) { *why = "cell side must exceed sigma"; return EC_E_INVALID; }
     int32_t nb = (int32_t)std::floor(w / p->sigma);
     if (nb < 3) { *why = "cell side below 3 sigma is not supported"; return EC_E_UNSUPPORTED; }
+    if (p->n_disks > (int64_t(1) << 29) - 4) {
+      *why = "walled cells support at most 2^29 - 4 disks"; return EC_E_UNSUPPORTED;
+    }
     out->w = w;
     out->nb = nb;
     out->cap_own = own_capacity(w, p->sigma);

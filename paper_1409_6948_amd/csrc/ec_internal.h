@@ -38,7 +38,8 @@ constexpr int kMaxDrawTries = 256;
 constexpr int kDebugWords = 16;
 
 constexpr int kDigestRing = 1024;
-// Events hashed together, one per lane, by the walled-cell kernel's digest.
+// Events hashed together, one per lane, by the walled-cell kernel's digest
+// (event ids then fit in 29 bits: N < 2^29 - 3).
 constexpr int kDigestBatch = 64;
 
 // Everything a kernel needs: device pointers into the caller's workspace and
@@ -74,9 +75,10 @@ struct Dev {
 
 // LDS layout of one simulation cell in the walled-cell kernel: per slot an
 // FP64 position and a 64-bit word (disk id | frozen bit, local own index);
-// then the own-disk tables and a ring of event records for the digest.
+// then the own-disk tables and one sink slot per lane (a target for the
+// lanes that do not store when one lane writes a position).
 struct CellLds {
-  int32_t off_pos, off_meta, off_mask, off_own_gid, off_own_loc, off_tmp, off_ring, bytes;
+  int32_t off_pos, off_meta, off_mask, off_own_gid, off_own_loc, off_tmp, off_sink, bytes;
 };
 
 __host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own) {
@@ -90,7 +92,7 @@ __host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own) {
   l.off_own_loc = o;  o += 4 * cap_own;
   l.off_tmp = o;      o += 4 * cap_own;
   o = (o + 15) & ~15;
-  l.off_ring = o;     o += 16 * kDigestBatch;
+  l.off_sink = o;     o += 16 * 64;
   l.bytes = (o + 15) & ~15;
   return l;
 }

@@ -250,15 +250,16 @@ __device__ __forceinline__ unsigned wave_xor_all(unsigned v) {
   return (unsigned)r32[0] ^ (unsigned)r32[1];
 }
 
-// Digest terms of the first `count` records of a ring (record k is event
-// first + k: x = bits(s), y = kind << 32 | id), XOR-ed over the wave.
-__device__ __forceinline__ uint64_t digest_batch(const ulonglong2* ring, int lane, int count,
-                                                 uint64_t first) {
+// Digest terms of the first `count` event records held one per lane (lane k:
+// record of event first + k, in three 32-bit registers: the step's bits and
+// kind << 29 | id), XOR-ed over the wave.
+__device__ __forceinline__ uint64_t digest_batch(uint32_t rec_lo, uint32_t rec_hi, uint32_t rec_tag,
+                                                 int lane, int count, uint64_t first) {
   uint64_t t = 0;
   if (lane < count) {
-    const ulonglong2 r = ring[lane];
-    t = digest_term((int)(r.y >> 32), r.y & 0xFFFFFFFFull, __longlong_as_double((long long)r.x),
-                    first + (uint64_t)lane);
+    const uint64_t sb = ((uint64_t)rec_hi << 32) | rec_lo;
+    t = digest_term((int)(rec_tag >> 29), rec_tag & 0x1FFFFFFFu,
+                    __longlong_as_double((long long)sb), first + (uint64_t)lane);
   }
   const uint32_t lo = (uint32_t)uniform_i32((int)wave_xor_all((uint32_t)t));
   const uint32_t hi = (uint32_t)uniform_i32((int)wave_xor_all((uint32_t)(t >> 32)));
@@ -536,7 +537,9 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
   int32_t* own_gid = (int32_t*)(base + lay.off_own_gid);
   int32_t* own_loc = (int32_t*)(base + lay.off_own_loc);
   int32_t* tmp = (int32_t*)(base + lay.off_tmp);
-  ulonglong2* ring = (ulonglong2*)(base + lay.off_ring);
+  // per-lane sink slots: lanes other than 0 write here when lane 0 stores the
+  // moved disk, so the store needs no change of the execution mask
+  double2* const sink = (double2*)(base + lay.off_sink) + lane;
 
   // ---- stage: own disks, sorted by id -----------------------------------
   const int start = d.cell_start[cell];
@@ -616,8 +619,9 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
   double acc = d.acc_delta[cell];
   uint32_t n_lift = 0, n_frozen = 0, n_wall = 0;
   uint64_t h = 0;
-  int n_ring = 0;          // event records waiting in the ring
-  uint64_t ring_first = 0;  // digest index of the ring's first record
+  int n_ring = 0;            // event records held in the lanes (lane k: record k)
+  uint64_t ring_first = 0;    // digest index of record 0
+  uint32_t rec_lo = 0, rec_hi = 0, rec_tag = 0;
   const int lx = lane & 3, ly = (lane >> 2) & 3, ks = lane >> 4;
   const int loff = ((ly * gridb) + lx) * 4 + ks;  // this lane's slot inside a window
   const double inv_b = d.inv_b;
@@ -770,12 +774,20 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
                                 : (kind == EV_WALL_X ? (uint32_t)wall_x_id
                                                      : (kind == EV_WALL_Y ? (uint32_t)wall_y_id
                                                                           : (wgid & ~kFrozenBit)));
-      const uint64_t rtag = ((uint64_t)(ends ? EV_END : kind) << 32) | eid;
-      const ulonglong2 rec = make_ulonglong2((unsigned long long)__double_as_longlong(step), rtag);
-      if (lane == 0) ring[n_ring] = rec;
+      {
+        // lane n_ring keeps this event's record (a select, no change of the
+        // execution mask)
+        const uint64_t sb = (uint64_t)__double_as_longlong(step);
+        const uint32_t tag = ((uint32_t)(ends ? EV_END : kind) << 29) | eid;
+        const bool mine = lane == n_ring;
+        rec_lo = mine ? (uint32_t)sb : rec_lo;
+        rec_hi = mine ? (uint32_t)(sb >> 32) : rec_hi;
+        rec_tag = mine ? tag : rec_tag;
+      }
       // store the moved disk; move it to another bin if it crossed a bin edge
       if (nbx == abx && nby == aby) {
-        if (lane == 0) pos[a_loc] = make_double2(ax, ay);
+        double2* const dst = (lane == 0) ? pos + a_loc : sink;
+        *dst = make_double2(ax, ay);
       } else {
         const int abin = aby * gridb + abx, nbin = nby * gridb + nbx;
         const int nm = uniform_i32(mask[nbin]);
@@ -799,7 +811,7 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
       }
       __builtin_amdgcn_wave_barrier();
       if (++n_ring == kDigestBatch) {
-        h ^= digest_batch(ring, lane, kDigestBatch, ring_first);
+        h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first);
         ring_first += kDigestBatch;
         n_ring = 0;
       }
@@ -871,7 +883,7 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
 
   // ---- write back: old position + local displacement, wrapped --------------
   wave_sync();
-  h ^= digest_batch(ring, lane, n_ring, ring_first);
+  h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, n_ring, ring_first);
   for (int k = lane; k < n_own; k += 64) {
     int g = own_gid[k];
     double2 v = pos[own_loc[k]];
