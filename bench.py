@@ -6,6 +6,12 @@ simulation cells, chain length 20 sigma, isotropic directions, FP64, starting
 from the lattice.  The metric is EC collisions (lifts) per second; sweeps per
 second and the whole-sweep fraction of HBM bandwidth are reported beside it.
 
+With --workload batch64 it times the batched form instead: the 64-system
+ensemble (N log-uniform in [4096, 262144], eta uniform in [0.30, 0.72], about
+64 disks per cell) advanced by shared launches, with the autotuned schedule
+and one HIP graph per sweep; the line reports aggregate lifts per second and
+the speed-up over running the same sweeps system by system.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                        [--no-cpu-baseline]
 """
@@ -94,6 +100,8 @@ def main():
     import torch
     import paper_1409_6948_amd as P
 
+    if args.workload == "batch64":
+        return bench_batch(args, torch, P)
     w = dict(inputs.WORKLOADS[args.workload])
     torch.cuda.set_device(0)
     p = P.make_params(w["n"], w["eta"], w["ell"], w["cells"], dir_mode=w["dir_mode"],
@@ -171,6 +179,75 @@ def main():
         line["cpu_baseline"] = cpu_baseline(w)
     else:
         line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+def bench_batch(args, torch, P):
+    """Aggregate lifts/s of the 64-system ensemble in the batched form, and the
+    same sweeps run system by system (solo launches, one system after another)."""
+    cfgs = inputs.batch_systems(64, seed=0)
+    ps = [P.make_params(c["n"], c["eta"], c["ell"], c["cells"], dir_mode=c["dir_mode"],
+                        seed=c["seed"], system=i) for i, c in enumerate(cfgs)]
+    torch.cuda.set_device(0)
+    b = P.Batch(ps)
+    print(f"# batch64: {len(ps)} systems, sum N = {sum(c['n'] for c in cfgs)}", file=sys.stderr,
+          flush=True)
+    b.sweep(1)
+    cpb, trials = b.autotune(trial_sweeps=2)
+    b.set_graph(True)
+    b.sweep(max(args.warmup - 1, 0))
+    b.stream.synchronize()
+    for s in b.systems:
+        s.reset_tallies()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.sweep(args.steps)
+    e1.record(b.stream)
+    b.stream.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3
+    lifts = 0
+    events = 0
+    for s in b.systems:
+        _, _, c = s.measure_pressure()
+        lifts += c["lifts"]
+        events += c["lifts"] + c["frozen"] + c["walls"] + c["chains"]
+    # the same sweeps, system by system
+    solo_secs = 0.0
+    st = torch.cuda.Stream()
+    for p in ps:
+        g = P.System(p, stream=st)
+        g.sweep(args.warmup)
+        st.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(st)
+        g.sweep(args.steps)
+        t1.record(st)
+        st.synchronize()
+        solo_secs += t0.elapsed_time(t1) / 1e3
+        g.close()
+    line = {
+        "metric": "EC collisions (lifts)/sec, 1 MI355X, 64-system batch (aggregate)",
+        "value": lifts / secs,
+        "unit": "lifts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batch64", "n_systems": len(ps),
+                   "sum_n": int(sum(c["n"] for c in cfgs)), "eta_range": [0.30, 0.72],
+                   "ell": 20.0, "cells_per_block": cpb, "hip_graph": True},
+        "events_per_s": events / secs,
+        "autotune_trial_ms": trials,
+        "solo_sequential_s": solo_secs,
+        "speedup_vs_solo_sequential": solo_secs / secs,
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -172,6 +172,61 @@ const char* ec_status_string(ec_status s);
 /* Text of the last error on this handle ("" if none); valid until the next call. */
 const char* ec_last_error(ec_system sys);
 
+/* ---- Batched form -------------------------------------------------------
+ * Several walled systems (C >= 4) advanced together: every step of a sweep
+ * (rebin, draws, each colour phase of Sec. 3.4) is one launch over all of
+ * them, so small systems fill the GPU together.  The schedule (shared
+ * launches, an optional HIP graph per sweep, cells per workgroup) never
+ * changes a trajectory: system i of a batch follows exactly the sweeps of a
+ * solo system with the same parameters (its seed and `system` index key its
+ * random streams).  Intended callers: ensembles of independent runs, such as
+ * a density scan.
+ */
+typedef struct ec_batch_s* ec_batch;
+
+/* Device bytes for a batch of n_sys systems ps[0..n_sys): their workspaces
+ * plus a snapshot area of the same size used by ec_batch_autotune.
+ * EC_E_INVALID / EC_E_UNSUPPORTED as ec_workspace_bytes, or for a periodic
+ * system (C = 1), or n_sys outside [1, 4096]. */
+ec_status ec_batch_workspace_bytes(const ec_params* ps, int32_t n_sys, size_t* bytes);
+
+/* Create the batch in dev_workspace (caller-owned, >= ec_batch_workspace_bytes)
+ * on hip_stream (borrowed).  Each system starts from its lattice as in
+ * ec_init_system; ps[i].cells_per_block is ignored (the batch schedule
+ * applies, initially 1).  Synchronises. */
+ec_status ec_init_batch(const ec_params* ps, int32_t n_sys, void* dev_workspace, size_t ws_bytes,
+                        void* hip_stream, ec_batch* out);
+
+/* Enqueue n_sweeps sweeps of every system (asynchronous). */
+ec_status ec_sweep_batch(ec_batch b, int64_t n_sweeps);
+
+/* Handle of system i for the queries of a single system (positions,
+ * pressure, digests, tallies, timing; ec_sweep advances that system alone).
+ * Owned by the batch: ec_destroy on it returns EC_E_STATE. */
+ec_status ec_batch_system(ec_batch b, int32_t i, ec_system* out);
+
+/* With on != 0, the first later sweep is captured into a HIP graph (kernels
+ * only) and every sweep replays it.  Needs a stream other than the null
+ * stream (EC_E_UNSUPPORTED). */
+ec_status ec_batch_set_graph(ec_batch b, int32_t on);
+
+/* Simulation cells per workgroup in the phase launches: 1, 2 or 4
+ * (EC_E_UNSUPPORTED if the LDS of that many cells exceeds 160 KiB). */
+ec_status ec_batch_set_cells_per_block(ec_batch b, int32_t cells_per_block);
+
+/* Time trial_sweeps sweeps for each cells-per-workgroup choice, each from a
+ * snapshot of the current state, keep the fastest and put the state back
+ * (sweep counts included): the batch continues as if no trial had run.
+ * cpb_out (may be NULL) receives the choice, ms_out[3] (may be NULL) the
+ * trial times for 1, 2, 4 (-1 where not allowed).  Synchronises. */
+ec_status ec_batch_autotune(ec_batch b, int32_t trial_sweeps, int32_t* cpb_out, double* ms_out);
+
+/* Text of the last batch-level error ("" if none). */
+const char* ec_batch_last_error(ec_batch b);
+
+/* Destroy the batch and its system handles (not the workspace).  Synchronises. */
+ec_status ec_destroy_batch(ec_batch b);
+
 #ifdef __cplusplus
 }
 #endif

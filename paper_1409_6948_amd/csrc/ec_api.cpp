@@ -19,8 +19,8 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 
 struct Layout {
-  size_t x, y, cell_of, cell_ids, cell_count, cell_fill, cell_start, acc_delta, acc_cnt, ring, cell_digest,
-      draws, err, red, chain_start, chain_dir, shuffle, dbg, total;
+  size_t dev, sweep_ctr, x, y, cell_of, cell_ids, cell_count, cell_fill, cell_start, acc_delta, acc_cnt,
+      ring, cell_digest, draws, err, red, chain_start, chain_dir, shuffle, dbg, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -31,6 +31,8 @@ Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell) {
   size_t nc = (size_t)C * (size_t)C;
   size_t max_chains = chains_per_cell > 0 ? nc * (size_t)chains_per_cell : (size_t)n;
   if (C == 1) max_chains = 0;  // the periodic kernel draws its chains itself
+  l.dev = o;        o = align256(o + sizeof(ec::Dev));
+  l.sweep_ctr = o;  o = align256(o + 8);
   l.x = o;          o = align256(o + 8 * (size_t)n);
   l.y = o;          o = align256(o + 8 * (size_t)n);
   l.cell_of = o;    o = align256(o + 4 * (size_t)n);
@@ -127,7 +129,10 @@ struct ec_system_s {
   ec_params p;
   Derived dv;
   Layout lay;
-  ec::Dev dev;
+  ec::Dev dev;           // host copy of the record kernels read from dev_d
+  ec::Dev* dev_d;        // device copy (in the workspace)
+  ec::LaunchShape shape; // this system alone
+  bool in_batch;         // owned by a batch (ec_destroy refuses it)
   hipStream_t stream;
   int64_t sweeps;
   std::string last_error;
@@ -182,14 +187,39 @@ ec_status ec_workspace_bytes(const ec_params* p, size_t* bytes) {
   return EC_OK;
 }
 
-ec_status ec_init_system(const ec_params* p, void* ws, size_t ws_bytes, void* stream,
-                         ec_system* out) {
-  if (!out || !ws) return EC_E_INVALID;
-  *out = nullptr;
-  Derived dv;
-  std::string why;
-  ec_status st = validate(p, &dv, &why);
-  if (st != EC_OK) return st;
+}  // extern "C"
+
+namespace {
+
+// Largest dynamic LDS the phase kernel may request (MI355X: 160 KiB per CU);
+// set once, outside any stream capture.
+hipError_t prepare_kernels() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  hipError_t e = ec::set_phase_lds_limit(160 * 1024);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+ec::LaunchShape shape_of(const ec::Dev& d, const ec_params& p) {
+  ec::LaunchShape sh;
+  sh.n_sys = 1;
+  sh.periodic = d.C == 1;
+  sh.any_distinct = d.start_mode == 1;
+  sh.max_n = d.n;
+  sh.max_chains = d.chains_per_cell > 0 ? (int64_t)d.C * d.C * d.chains_per_cell : d.n;
+  sh.max_cells = d.C * d.C;
+  sh.max_active = (d.C / 2) * (d.C / 2);
+  sh.cpb = d.cells_per_block;
+  sh.max_lds_per_cell = d.lds_per_cell;
+  (void)p;
+  return sh;
+}
+
+// Create a system in a workspace region (validated parameters); with a
+// batch owner the handle is a view that the batch destroys.
+ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b, size_t ws_bytes,
+                         hipStream_t stream, bool in_batch, ec_system* out) {
   Layout lay = make_layout(p->n_disks, p->cells_per_side, p->chains_per_cell);
   if (ws_bytes < lay.total) return EC_E_NOMEM;
   ec_system s = new (std::nothrow) ec_system_s();
@@ -197,13 +227,14 @@ ec_status ec_init_system(const ec_params* p, void* ws, size_t ws_bytes, void* st
   s->p = *p;
   s->dv = dv;
   s->lay = lay;
-  s->stream = (hipStream_t)stream;
+  s->stream = stream;
+  s->in_batch = in_batch;
   s->sweeps = 0;
   s->timing = false;
   s->phase_ms = 0.0;
   s->phase_launches = 0;
-  unsigned char* b = (unsigned char*)ws;
   ec::Dev& d = s->dev;
+  std::memset(&d, 0, sizeof d);
   d.x = (double*)(b + lay.x);
   d.y = (double*)(b + lay.y);
   d.cell_of = (int32_t*)(b + lay.cell_of);
@@ -222,6 +253,7 @@ ec_status ec_init_system(const ec_params* p, void* ws, size_t ws_bytes, void* st
   d.chain_dir = (double2*)(b + lay.chain_dir);
   d.shuffle = (int32_t*)(b + lay.shuffle);
   d.dbg = (double*)(b + lay.dbg);
+  d.sweep_ctr = (int64_t*)(b + lay.sweep_ctr);
   d.search = (p->flags & EC_FLAG_SCAN_SEARCH) ? 1 : 0;
   d.n = p->n_disks;
   d.sigma = p->sigma;
@@ -246,17 +278,22 @@ ec_status ec_init_system(const ec_params* p, void* ws, size_t ws_bytes, void* st
   d.cells_per_block = dv.cpb;
   d.seed = p->seed;
   d.system = p->system;
+  s->dev_d = (ec::Dev*)(b + lay.dev);
+  s->shape = shape_of(d, *p);
 
   int64_t k = (int64_t)std::ceil(std::sqrt((double)p->n_disks));
   while (k * k < p->n_disks) ++k;
   double a = dv.L / (double)k;
-  hipError_t e = ec::launch_lattice(d, k, a, s->stream);
-  if (e == hipSuccess) e = ec::launch_zero_tallies(d, s->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(d.err, 0, 8, s->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(d.dbg, 0, 8 * ec::kDebugWords, s->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(d.digest_ring, 0, 8 * ec::kDigestRing, s->stream);
-  if (e == hipSuccess)
-    e = hipMemsetAsync(d.cell_digest, 0, 8 * (size_t)d.C * (size_t)d.C, s->stream);
+  hipError_t e = prepare_kernels();
+  if (e == hipSuccess) e = hipMemcpyAsync(s->dev_d, &s->dev, sizeof(ec::Dev), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.sweep_ctr, 0, 8, stream);
+  if (e == hipSuccess) e = ec::launch_lattice(s->dev_d, d.n, k, a, stream);
+  if (e == hipSuccess) e = ec::launch_zero_tallies(s->dev_d, d.C * d.C, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.err, 0, 8, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.dbg, 0, 8 * ec::kDebugWords, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.digest_ring, 0, 8 * ec::kDigestRing, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.cell_digest, 0, 8 * (size_t)d.C * (size_t)d.C, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // the host record is copied by now
   if (e != hipSuccess) {
     ec_status r = hip_fail(s, e, "init");
     delete s;
@@ -266,11 +303,26 @@ ec_status ec_init_system(const ec_params* p, void* ws, size_t ws_bytes, void* st
   return EC_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+ec_status ec_init_system(const ec_params* p, void* ws, size_t ws_bytes, void* stream,
+                         ec_system* out) {
+  if (!out || !ws) return EC_E_INVALID;
+  *out = nullptr;
+  Derived dv;
+  std::string why;
+  ec_status st = validate(p, &dv, &why);
+  if (st != EC_OK) return st;
+  return init_system_at(p, dv, (unsigned char*)ws, ws_bytes, (hipStream_t)stream, false, out);
+}
+
 ec_status ec_sweep(ec_system s, int64_t n_sweeps) {
   if (!s || n_sweeps < 0) return EC_E_INVALID;
   for (int64_t i = 0; i < n_sweeps; ++i) {
     if (s->timing) {
-      EC_HIP(s, ec::launch_sweep(s->dev, s->sweeps, s->stream, &s->ev));
+      EC_HIP(s, ec::launch_sweep(s->dev_d, s->shape, s->stream, &s->ev));
       EC_HIP(s, hipStreamSynchronize(s->stream));
       int nq = s->p.cells_per_side == 1 ? 1 : 4;
       for (int q = 0; q < nq; ++q) {
@@ -280,7 +332,7 @@ ec_status ec_sweep(ec_system s, int64_t n_sweeps) {
         s->phase_launches += 1;
       }
     } else {
-      EC_HIP(s, ec::launch_sweep(s->dev, s->sweeps, s->stream));
+      EC_HIP(s, ec::launch_sweep(s->dev_d, s->shape, s->stream));
     }
     s->sweeps += 1;
   }
@@ -339,7 +391,7 @@ static ec_status check_err(ec_system s) {
 
 ec_status ec_measure_pressure(ec_system s, double* z, double* bp, uint64_t* counts) {
   if (!s) return EC_E_INVALID;
-  EC_HIP(s, ec::launch_reduce(s->dev, s->stream));
+  EC_HIP(s, ec::launch_reduce(s->dev_d, s->stream));
   double red[8];
   EC_HIP(s, hipMemcpyAsync(red, s->dev.red, sizeof red, hipMemcpyDeviceToHost, s->stream));
   ec_status st = check_err(s);
@@ -356,7 +408,7 @@ ec_status ec_measure_pressure(ec_system s, double* z, double* bp, uint64_t* coun
 
 ec_status ec_reset_tallies(ec_system s) {
   if (!s) return EC_E_INVALID;
-  EC_HIP(s, ec::launch_zero_tallies(s->dev, s->stream));
+  EC_HIP(s, ec::launch_zero_tallies(s->dev_d, s->p.cells_per_side * s->p.cells_per_side, s->stream));
   return EC_OK;
 }
 
@@ -457,9 +509,289 @@ ec_status ec_get_sweep_count(ec_system s, int64_t* sweeps) {
 
 ec_status ec_destroy(ec_system s) {
   if (!s) return EC_E_INVALID;
+  if (s->in_batch) return EC_E_STATE;  // views are destroyed with their batch
   if (s->timing) ec_set_timing(s, 0);
   hipError_t e = hipStreamSynchronize(s->stream);
   delete s;
+  return e == hipSuccess ? EC_OK : EC_E_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Batched form: several walled systems advanced by shared launches
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct ec_batch_s {
+  std::vector<ec_system> sys;
+  std::vector<size_t> off;      // byte offset of each system's region
+  unsigned char* ws;
+  size_t sys_bytes;             // bytes of all system regions (snapshot size)
+  ec::Dev* devs_d;              // device array of the systems' records
+  ec::LaunchShape shape;
+  hipStream_t stream;
+  bool use_graph;
+  bool graph_ready;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  std::string last_error;
+};
+
+namespace {
+
+constexpr int32_t kMaxBatch = 4096;
+
+struct BatchLayout {
+  size_t devs, systems, snapshot, total;
+  std::vector<size_t> off;
+};
+
+ec_status batch_layout(const ec_params* ps, int32_t n, BatchLayout* bl, std::vector<Derived>* dvs,
+                       std::string* why) {
+  if (!ps || n < 1 || n > kMaxBatch) { *why = "batch size out of range"; return EC_E_INVALID; }
+  size_t o = 0;
+  bl->devs = o;
+  o = align256(o + sizeof(ec::Dev) * (size_t)n);
+  bl->systems = o;
+  bl->off.resize((size_t)n);
+  dvs->resize((size_t)n);
+  for (int32_t i = 0; i < n; ++i) {
+    ec_status st = validate(&ps[i], &(*dvs)[(size_t)i], why);
+    if (st != EC_OK) return st;
+    if (ps[i].cells_per_side == 1) { *why = "batches hold walled systems (C >= 4) only"; return EC_E_UNSUPPORTED; }
+    bl->off[(size_t)i] = o;
+    o = align256(o + make_layout(ps[i].n_disks, ps[i].cells_per_side, ps[i].chains_per_cell).total);
+  }
+  size_t sys_bytes = o - bl->systems;
+  bl->snapshot = o;
+  o = align256(o + sys_bytes);
+  bl->total = o;
+  return EC_OK;
+}
+
+// Upload the records with the batch's schedule and drop any captured graph.
+ec_status batch_sync_records(ec_batch b) {
+  std::vector<ec::Dev> h(b->sys.size());
+  for (size_t i = 0; i < b->sys.size(); ++i) {
+    b->sys[i]->dev.cells_per_block = b->shape.cpb;
+    b->sys[i]->shape.cpb = b->shape.cpb;
+    h[i] = b->sys[i]->dev;
+  }
+  hipError_t e = hipMemcpyAsync(b->devs_d, h.data(), sizeof(ec::Dev) * h.size(), hipMemcpyHostToDevice,
+                                b->stream);
+  for (size_t i = 0; i < b->sys.size() && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(b->sys[i]->dev_d, &h[i], sizeof(ec::Dev), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // h is a local
+  if (b->graph_ready) {
+    hipGraphExecDestroy(b->exec);
+    hipGraphDestroy(b->graph);
+    b->graph_ready = false;
+  }
+  if (e != hipSuccess) {
+    b->last_error = std::string("batch records: ") + hipGetErrorString(e);
+    return EC_E_HIP;
+  }
+  return EC_OK;
+}
+
+ec_status batch_fail(ec_batch b, hipError_t e, const char* what) {
+  b->last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return EC_E_HIP;
+}
+
+ec_status batch_sweeps(ec_batch b, int64_t n) {
+  if (b->use_graph) {
+    if (!b->graph_ready) {
+      hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return batch_fail(b, e, "begin capture");
+      hipError_t el = ec::launch_sweep(b->devs_d, b->shape, b->stream);
+      e = hipStreamEndCapture(b->stream, &b->graph);
+      if (el != hipSuccess) return batch_fail(b, el, "captured sweep");
+      if (e != hipSuccess) return batch_fail(b, e, "end capture");
+      e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        hipGraphDestroy(b->graph);
+        return batch_fail(b, e, "instantiate");
+      }
+      b->graph_ready = true;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      hipError_t e = hipGraphLaunch(b->exec, b->stream);
+      if (e != hipSuccess) return batch_fail(b, e, "graph launch");
+    }
+  } else {
+    for (int64_t i = 0; i < n; ++i) {
+      hipError_t e = ec::launch_sweep(b->devs_d, b->shape, b->stream);
+      if (e != hipSuccess) return batch_fail(b, e, "sweep");
+    }
+  }
+  for (auto* s : b->sys) s->sweeps += n;
+  return EC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ec_status ec_batch_workspace_bytes(const ec_params* ps, int32_t n_sys, size_t* bytes) {
+  if (!bytes) return EC_E_INVALID;
+  BatchLayout bl;
+  std::vector<Derived> dvs;
+  std::string why;
+  ec_status st = batch_layout(ps, n_sys, &bl, &dvs, &why);
+  if (st != EC_OK) return st;
+  *bytes = bl.total;
+  return EC_OK;
+}
+
+ec_status ec_init_batch(const ec_params* ps, int32_t n_sys, void* ws, size_t ws_bytes, void* stream,
+                        ec_batch* out) {
+  if (!out || !ws) return EC_E_INVALID;
+  *out = nullptr;
+  BatchLayout bl;
+  std::vector<Derived> dvs;
+  std::string why;
+  ec_status st = batch_layout(ps, n_sys, &bl, &dvs, &why);
+  if (st != EC_OK) return st;
+  if (ws_bytes < bl.total) return EC_E_NOMEM;
+  ec_batch b = new (std::nothrow) ec_batch_s();
+  if (!b) return EC_E_NOMEM;
+  b->ws = (unsigned char*)ws;
+  b->off = bl.off;
+  b->sys_bytes = bl.snapshot - bl.systems;
+  b->devs_d = (ec::Dev*)(b->ws + bl.devs);
+  b->stream = (hipStream_t)stream;
+  b->use_graph = false;
+  b->graph_ready = false;
+  ec::LaunchShape& sh = b->shape;
+  std::memset(&sh, 0, sizeof sh);
+  sh.n_sys = n_sys;
+  sh.periodic = false;
+  sh.cpb = 1;
+  for (int32_t i = 0; i < n_sys; ++i) {
+    ec_params p = ps[i];
+    p.cells_per_block = 1;
+    ec_system s = nullptr;
+    size_t region = (i + 1 < n_sys ? bl.off[(size_t)i + 1] : bl.snapshot) - bl.off[(size_t)i];
+    st = init_system_at(&p, dvs[(size_t)i], b->ws + bl.off[(size_t)i], region, b->stream, true, &s);
+    if (st != EC_OK) {
+      b->last_error = "system " + std::to_string(i) + ": init failed";
+      for (auto* v : b->sys) delete v;
+      delete b;
+      return st;
+    }
+    b->sys.push_back(s);
+    const ec::LaunchShape& one = s->shape;
+    sh.any_distinct = sh.any_distinct || one.any_distinct;
+    sh.max_n = std::max(sh.max_n, one.max_n);
+    sh.max_chains = std::max(sh.max_chains, one.max_chains);
+    sh.max_cells = std::max(sh.max_cells, one.max_cells);
+    sh.max_active = std::max(sh.max_active, one.max_active);
+    sh.max_lds_per_cell = std::max(sh.max_lds_per_cell, one.max_lds_per_cell);
+  }
+  st = batch_sync_records(b);
+  if (st != EC_OK) {
+    for (auto* v : b->sys) delete v;
+    delete b;
+    return st;
+  }
+  *out = b;
+  return EC_OK;
+}
+
+ec_status ec_sweep_batch(ec_batch b, int64_t n_sweeps) {
+  if (!b || n_sweeps < 0) return EC_E_INVALID;
+  return batch_sweeps(b, n_sweeps);
+}
+
+ec_status ec_batch_system(ec_batch b, int32_t i, ec_system* out) {
+  if (!b || !out || i < 0 || i >= (int32_t)b->sys.size()) return EC_E_INVALID;
+  *out = b->sys[(size_t)i];
+  return EC_OK;
+}
+
+ec_status ec_batch_set_graph(ec_batch b, int32_t on) {
+  if (!b) return EC_E_INVALID;
+  if (on && b->stream == nullptr) {
+    b->last_error = "graph capture needs a stream other than the null stream";
+    return EC_E_UNSUPPORTED;
+  }
+  b->use_graph = on != 0;
+  return EC_OK;
+}
+
+ec_status ec_batch_set_cells_per_block(ec_batch b, int32_t cpb) {
+  if (!b) return EC_E_INVALID;
+  if (cpb != 1 && cpb != 2 && cpb != 4) return EC_E_INVALID;
+  if ((size_t)cpb * (size_t)b->shape.max_lds_per_cell > 160 * 1024) return EC_E_UNSUPPORTED;
+  b->shape.cpb = cpb;
+  return batch_sync_records(b);
+}
+
+ec_status ec_batch_autotune(ec_batch b, int32_t trial_sweeps, int32_t* cpb_out, double* ms_out) {
+  if (!b || trial_sweeps < 1) return EC_E_INVALID;
+  // the trials run from a snapshot of every system's state, which is put back
+  // afterwards: the schedule changes timing only, never the trajectory
+  unsigned char* sys0 = b->ws + b->off[0];
+  unsigned char* snap = sys0 + b->sys_bytes;
+  std::vector<int64_t> sweeps0;
+  for (auto* s : b->sys) sweeps0.push_back(s->sweeps);
+  hipError_t e = hipMemcpyAsync(snap, sys0, b->sys_bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e != hipSuccess) return batch_fail(b, e, "snapshot");
+  hipEvent_t t0, t1;
+  if ((e = hipEventCreate(&t0)) != hipSuccess) return batch_fail(b, e, "event");
+  if ((e = hipEventCreate(&t1)) != hipSuccess) { hipEventDestroy(t0); return batch_fail(b, e, "event"); }
+  const int32_t cands[3] = {1, 2, 4};
+  int32_t best = b->shape.cpb;
+  double best_ms = 0.0;
+  ec_status st = EC_OK;
+  for (int c = 0; c < 3 && st == EC_OK; ++c) {
+    double ms_c = -1.0;
+    if ((size_t)cands[c] * (size_t)b->shape.max_lds_per_cell <= 160 * 1024) {
+      b->shape.cpb = cands[c];
+      st = batch_sync_records(b);
+      if (st != EC_OK) break;
+      e = hipMemcpyAsync(sys0, snap, b->sys_bytes, hipMemcpyDeviceToDevice, b->stream);
+      if (e == hipSuccess) st = batch_sweeps(b, 1);  // warm-up (graph capture, caches)
+      if (e == hipSuccess && st == EC_OK) e = hipMemcpyAsync(sys0, snap, b->sys_bytes, hipMemcpyDeviceToDevice, b->stream);
+      if (e == hipSuccess && st == EC_OK) e = hipEventRecord(t0, b->stream);
+      if (e == hipSuccess && st == EC_OK) st = batch_sweeps(b, trial_sweeps);
+      if (e == hipSuccess && st == EC_OK) e = hipEventRecord(t1, b->stream);
+      if (e == hipSuccess && st == EC_OK) e = hipEventSynchronize(t1);
+      float ms = 0.f;
+      if (e == hipSuccess && st == EC_OK) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e != hipSuccess) { st = batch_fail(b, e, "autotune trial"); break; }
+      ms_c = ms;
+      if (best_ms == 0.0 || ms < best_ms) { best_ms = ms; best = cands[c]; }
+    }
+    if (ms_out) ms_out[c] = ms_c;
+  }
+  hipEventDestroy(t0);
+  hipEventDestroy(t1);
+  // back to the snapshot with the chosen schedule
+  e = hipMemcpyAsync(sys0, snap, b->sys_bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e != hipSuccess && st == EC_OK) st = batch_fail(b, e, "restore");
+  for (size_t i = 0; i < b->sys.size(); ++i) b->sys[i]->sweeps = sweeps0[i];
+  b->shape.cpb = best;
+  ec_status st2 = batch_sync_records(b);
+  if (st == EC_OK) st = st2;
+  if (cpb_out) *cpb_out = best;
+  return st;
+}
+
+const char* ec_batch_last_error(ec_batch b) { return b ? b->last_error.c_str() : ""; }
+
+ec_status ec_destroy_batch(ec_batch b) {
+  if (!b) return EC_E_INVALID;
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (b->graph_ready) {
+    hipGraphExecDestroy(b->exec);
+    hipGraphDestroy(b->graph);
+  }
+  for (auto* s : b->sys) {
+    if (s->timing) { s->in_batch = false; ec_set_timing(s, 0); }
+    delete s;
+  }
+  delete b;
   return e == hipSuccess ? EC_OK : EC_E_HIP;
 }
 

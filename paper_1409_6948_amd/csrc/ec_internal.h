@@ -63,6 +63,7 @@ struct Dev {
   double2* chain_dir;               // [max chains per sweep] direction of each chain
   int32_t* shuffle;                 // [N] per-cell shuffled lists (distinct-start mode)
   double* dbg;                      // [kDebugWords] state of the first wave that tripped a cap
+  int64_t* sweep_ctr;               // [1] sweeps done; read by every kernel of a sweep
 
   int64_t n;
   double sigma, sig2, ell, L, half_L, w, cap, b, inv_b, margin;
@@ -100,15 +101,34 @@ __host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own) {
 // Largest N the one-periodic-cell kernel keeps in LDS.
 constexpr int64_t kPeriodicMaxN = 2048;
 
-hipError_t launch_lattice(const Dev& d, int64_t k, double a, hipStream_t st);
+// Extents of one launch over n_sys systems whose Dev records are in device
+// memory (ds[0..n_sys)): maxima over the systems, and the shared schedule.
+struct LaunchShape {
+  int32_t n_sys;
+  bool periodic;            // one periodic cell (single system only)
+  bool any_distinct;        // some system uses the distinct-start control
+  int64_t max_n;            // disks
+  int64_t max_chains;       // chains per sweep
+  int32_t max_cells;        // C * C
+  int32_t max_active;       // C * C / 4
+  int32_t cpb;              // simulation cells per workgroup (same for all)
+  int32_t max_lds_per_cell; // bytes
+};
+
 // Optional HIP events recorded around every phase launch (begin[q], end[q]).
 struct PhaseEvents {
   hipEvent_t begin[4], end[4];
 };
 
-hipError_t launch_sweep(const Dev& d, int64_t sweep, hipStream_t st,
+hipError_t launch_lattice(const Dev* ds, int64_t n, int64_t k, double a, hipStream_t st);
+// One sweep of every system in ds: rebin, draws, four colour phases (or the
+// periodic kernel), then the sweep counters advance.  Kernels only (no memset
+// or copy), so the sequence can be captured in a HIP graph and replayed.
+hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
                         const PhaseEvents* ev = nullptr);
-hipError_t launch_reduce(const Dev& d, hipStream_t st);
-hipError_t launch_zero_tallies(const Dev& d, hipStream_t st);
+hipError_t launch_reduce(const Dev* ds, hipStream_t st);
+// Allow the phase kernel up to `bytes` of dynamic LDS per workgroup.
+hipError_t set_phase_lds_limit(int bytes);
+hipError_t launch_zero_tallies(const Dev* ds, int32_t n_cells, hipStream_t st);
 
 }  // namespace ec

@@ -301,7 +301,8 @@ __device__ __forceinline__ double local_coord(double p, double shift, double ori
 // ---------------------------------------------------------------------------
 // Start lattice
 // ---------------------------------------------------------------------------
-__global__ void k_lattice(Dev d, int64_t k, double a) {
+__global__ void k_lattice(const Dev* __restrict__ ds, int64_t k, double a) {
+  const Dev d = ds[blockIdx.y];
   int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= d.n) return;
   int64_t j = id / k, i = id % k;
@@ -325,7 +326,9 @@ __device__ void decode_perm(uint64_t idx, int32_t* perm) {
   }
 }
 
-__global__ void k_prep(Dev d, int64_t sweep) {
+__global__ void k_prep(const Dev* __restrict__ ds) {
+  const Dev d = ds[blockIdx.y];
+  const int64_t sweep = *d.sweep_ctr;
   int ncell = d.C * d.C;
   for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
     d.cell_count[c] = 0;
@@ -351,7 +354,8 @@ __device__ __forceinline__ int cell_of_pos(const Dev& d, double px, double py, d
   return cy * d.C + cx;
 }
 
-__global__ void k_count(Dev d) {
+__global__ void k_count(const Dev* __restrict__ ds) {
+  const Dev d = ds[blockIdx.y];
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   SweepDraws dr = *d.draws;
@@ -361,7 +365,8 @@ __global__ void k_count(Dev d) {
 }
 
 // Exclusive prefix sum of the cell counts, one workgroup of 1024 threads.
-__global__ void __launch_bounds__(1024) k_scan(Dev d) {
+__global__ void __launch_bounds__(1024) k_scan(const Dev* __restrict__ ds) {
+  const Dev d = ds[blockIdx.y];
   __shared__ int32_t part[1024];
   int ncell = d.C * d.C;
   int per = (ncell + 1023) / 1024;
@@ -384,7 +389,8 @@ __global__ void __launch_bounds__(1024) k_scan(Dev d) {
   if (threadIdx.x == 1023) d.cell_start[ncell] = part[1023];
 }
 
-__global__ void k_scatter(Dev d) {
+__global__ void k_scatter(const Dev* __restrict__ ds) {
+  const Dev d = ds[blockIdx.y];
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   int c = d.cell_of[i];
@@ -451,7 +457,10 @@ __device__ __forceinline__ int cell_of_slot(const Dev& d, int64_t i) {
   return lo;
 }
 
-__global__ void k_draws(Dev d, int64_t sweep, int64_t total) {
+__global__ void k_draws(const Dev* __restrict__ ds) {
+  const Dev d = ds[blockIdx.y];
+  const int64_t sweep = *d.sweep_ctr;
+  const int64_t total = d.chains_per_cell > 0 ? (int64_t)d.C * d.C * d.chains_per_cell : d.n;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   int cell;
@@ -480,7 +489,10 @@ __global__ void k_draws(Dev d, int64_t sweep, int64_t total) {
 
 // Distinct-start negative control: one thread per cell shuffles [0, n_c)
 // (Fisher-Yates) and chain k starts at list[k mod n_c].
-__global__ void k_shuffle(Dev d, int64_t sweep) {
+__global__ void k_shuffle(const Dev* __restrict__ ds) {
+  const Dev d = ds[blockIdx.y];
+  if (d.start_mode != 1) return;
+  const int64_t sweep = *d.sweep_ctr;
   int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= d.C * d.C) return;
   int s0 = d.cell_start[cell];
@@ -511,7 +523,9 @@ __device__ __forceinline__ int32_t load_err(const Dev& d) {
   return __hip_atomic_load(d.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
+__global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q) {
+  const Dev d = ds[blockIdx.y];
+  const int64_t sweep = *d.sweep_ctr;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -913,7 +927,9 @@ __global__ void __launch_bounds__(256) k_phase(Dev d, int64_t sweep, int q) {
 // One periodic cell (C = 1): all N disks in LDS, brute-force search with the
 // minimum image; flights longer than L/2 - sigma are split (free-flight cap).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_periodic(Dev d, int64_t sweep) {
+__global__ void __launch_bounds__(64) k_periodic(const Dev* __restrict__ ds) {
+  const Dev d = ds[blockIdx.y];
+  const int64_t sweep = *d.sweep_ctr;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int lane = threadIdx.x;
   const int n = (int)d.n;
@@ -1019,7 +1035,8 @@ __global__ void __launch_bounds__(64) k_periodic(Dev d, int64_t sweep) {
 // ---------------------------------------------------------------------------
 // Tallies
 // ---------------------------------------------------------------------------
-__global__ void k_reduce(Dev d) {
+__global__ void k_reduce(const Dev* __restrict__ ds) {
+  const Dev d = ds[blockIdx.y];
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int ncell = d.C * d.C;
   double s = 0.0;
@@ -1032,7 +1049,8 @@ __global__ void k_reduce(Dev d) {
   for (int k = 0; k < CNT_NCOL; ++k) d.red[1 + k] = __longlong_as_double((long long)c[k]);
 }
 
-__global__ void k_zero_tallies(Dev d) {
+__global__ void k_zero_tallies(const Dev* __restrict__ ds) {
+  const Dev d = ds[blockIdx.y];
   int ncell = d.C * d.C;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += gridDim.x * blockDim.x) {
     d.acc_delta[i] = 0.0;
@@ -1040,63 +1058,70 @@ __global__ void k_zero_tallies(Dev d) {
   }
 }
 
+// The sweep counter every kernel of the next sweep reads (one thread per system).
+__global__ void k_sweep_done(const Dev* __restrict__ ds) {
+  if (threadIdx.x == 0) *ds[blockIdx.y].sweep_ctr += 1;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_lattice(const Dev& d, int64_t k, double a, hipStream_t st) {
-  int64_t blocks = (d.n + 255) / 256;
-  hipLaunchKernelGGL(k_lattice, dim3((unsigned)blocks), dim3(256), 0, st, d, k, a);
+// Grid x-extents are the maxima over the systems of a launch (gridDim.y =
+// systems); blocks beyond a system's own extent leave at once.
+// ---------------------------------------------------------------------------
+hipError_t launch_lattice(const Dev* ds, int64_t n, int64_t k, double a, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_lattice, dim3((unsigned)blocks), dim3(256), 0, st, ds, k, a);
   return hipGetLastError();
 }
 
-hipError_t launch_zero_tallies(const Dev& d, hipStream_t st) {
-  int ncell = d.C * d.C;
-  int blocks = (ncell + 255) / 256;
-  hipLaunchKernelGGL(k_zero_tallies, dim3(blocks), dim3(256), 0, st, d);
+hipError_t launch_zero_tallies(const Dev* ds, int32_t n_cells, hipStream_t st) {
+  int blocks = (n_cells + 255) / 256;
+  hipLaunchKernelGGL(k_zero_tallies, dim3(blocks), dim3(256), 0, st, ds);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const Dev& d, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, st, d);
+hipError_t set_phase_lds_limit(int bytes) {
+  return hipFuncSetAttribute((const void*)k_phase, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t launch_reduce(const Dev* ds, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, st, ds);
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(const Dev& d, int64_t sweep, hipStream_t st, const PhaseEvents* ev) {
-  if (d.C == 1) {
-    size_t lds = (size_t)d.n * 16 + (size_t)d.n * 4;
+hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
+                        const PhaseEvents* ev) {
+  const unsigned ns = (unsigned)sh.n_sys;
+  if (sh.periodic) {
+    size_t lds = (size_t)sh.max_n * 16 + (size_t)sh.max_n * 4;
     if (ev) hipEventRecord(ev->begin[0], st);
-    hipLaunchKernelGGL(k_periodic, dim3(1), dim3(64), lds, st, d, sweep);
+    hipLaunchKernelGGL(k_periodic, dim3(1, ns), dim3(64), lds, st, ds);
     if (ev) hipEventRecord(ev->end[0], st);
+    hipLaunchKernelGGL(k_sweep_done, dim3(1, ns), dim3(64), 0, st, ds);
     return hipGetLastError();
   }
-  unsigned nblk = (unsigned)((d.n + 255) / 256);
-  hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, d, sweep);
-  hipLaunchKernelGGL(k_count, dim3(nblk), dim3(256), 0, st, d);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d);
-  hipLaunchKernelGGL(k_scatter, dim3(nblk), dim3(256), 0, st, d);
-  int64_t total = d.chains_per_cell > 0 ? (int64_t)d.C * d.C * d.chains_per_cell : d.n;
-  hipLaunchKernelGGL(k_draws, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, d, sweep,
-                     total);
-  if (d.start_mode == 1)
-    hipLaunchKernelGGL(k_shuffle, dim3((unsigned)((d.C * d.C + 63) / 64)), dim3(64), 0, st, d,
-                       sweep);
-  int half = d.C / 2;
-  int active = half * half;
-  int cpb = d.cells_per_block;
-  unsigned grid = (unsigned)((active + cpb - 1) / cpb);
-  size_t lds = (size_t)cpb * d.lds_per_cell;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_phase,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
+  const unsigned nblk = (unsigned)((sh.max_n + 255) / 256);
+  hipLaunchKernelGGL(k_prep, dim3(1, ns), dim3(1024), 0, st, ds);
+  hipLaunchKernelGGL(k_count, dim3(nblk, ns), dim3(256), 0, st, ds);
+  hipLaunchKernelGGL(k_scan, dim3(1, ns), dim3(1024), 0, st, ds);
+  hipLaunchKernelGGL(k_scatter, dim3(nblk, ns), dim3(256), 0, st, ds);
+  hipLaunchKernelGGL(k_draws, dim3((unsigned)((sh.max_chains + 255) / 256), ns), dim3(256), 0, st,
+                     ds);
+  if (sh.any_distinct)
+    hipLaunchKernelGGL(k_shuffle, dim3((unsigned)((sh.max_cells + 63) / 64), ns), dim3(64), 0, st,
+                       ds);
+  const int cpb = sh.cpb;
+  const unsigned grid = (unsigned)((sh.max_active + cpb - 1) / cpb);
+  const size_t lds = (size_t)cpb * sh.max_lds_per_cell;
   for (int q = 0; q < 4; ++q) {
     if (ev) hipEventRecord(ev->begin[q], st);
-    hipLaunchKernelGGL(k_phase, dim3(grid), dim3(64 * cpb), lds, st, d, sweep, q);
+    hipLaunchKernelGGL(k_phase, dim3(grid, ns), dim3(64 * cpb), lds, st, ds, q);
     if (ev) hipEventRecord(ev->end[q], st);
   }
+  hipLaunchKernelGGL(k_sweep_done, dim3(1, ns), dim3(64), 0, st, ds);
   return hipGetLastError();
 }
 

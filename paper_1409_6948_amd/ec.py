@@ -25,7 +25,9 @@ EXPORTED = ("ec_workspace_bytes", "ec_init_system", "ec_sweep", "ec_measure_pres
             "ec_reset_tallies", "ec_get_positions", "ec_set_positions", "ec_get_digests",
             "ec_get_cell_tallies", "ec_get_cell_digests", "ec_get_sweep_count",
             "ec_set_timing", "ec_get_timing", "ec_destroy", "ec_status_string",
-            "ec_last_error")
+            "ec_last_error", "ec_batch_workspace_bytes", "ec_init_batch", "ec_sweep_batch",
+            "ec_batch_system", "ec_batch_set_graph", "ec_batch_set_cells_per_block",
+            "ec_batch_autotune", "ec_batch_last_error", "ec_destroy_batch")
 
 
 class ECError(RuntimeError):
@@ -76,6 +78,14 @@ def load_library():
         "ec_set_timing": [vp, C.c_int32],
         "ec_get_timing": [vp, dp, C.POINTER(C.c_int64)],
         "ec_destroy": [vp],
+        "ec_batch_workspace_bytes": [P, C.c_int32, C.POINTER(C.c_size_t)],
+        "ec_init_batch": [P, C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)],
+        "ec_sweep_batch": [vp, C.c_int64],
+        "ec_batch_system": [vp, C.c_int32, C.POINTER(vp)],
+        "ec_batch_set_graph": [vp, C.c_int32],
+        "ec_batch_set_cells_per_block": [vp, C.c_int32],
+        "ec_batch_autotune": [vp, C.c_int32, C.POINTER(C.c_int32), dp],
+        "ec_destroy_batch": [vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -85,6 +95,8 @@ def load_library():
     L.ec_status_string.restype = C.c_char_p
     L.ec_last_error.argtypes = [vp]
     L.ec_last_error.restype = C.c_char_p
+    L.ec_batch_last_error.argtypes = [vp]
+    L.ec_batch_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -97,12 +109,12 @@ def make_params(n, eta, ell, cells, dir_mode=EC_DIR_ISOTROPIC, seed=1, sigma=1.0
                   int(cells_per_block), float(screen_margin), int(seed), int(system), 0)
 
 
-def _check(status, handle=None, what=""):
+def _check(status, handle=None, what="", batch=False):
     if status != EC_OK:
         L = load_library()
         msg = L.ec_status_string(status).decode()
         if handle:
-            extra = L.ec_last_error(handle).decode()
+            extra = (L.ec_batch_last_error if batch else L.ec_last_error)(handle).decode()
             if extra:
                 msg += ": " + extra
         raise ECError(status, f"{what}: {msg}")
@@ -125,11 +137,15 @@ class System:
     current stream unless one is given.
     """
 
-    def __init__(self, p, device="cuda", stream=None):
-        import torch
+    def __init__(self, p, device="cuda", stream=None, _view=None):
         self._lib = load_library()
         self.p = p
         self.n = int(p.n_disks)
+        if _view is not None:  # a system of a Batch (the batch owns handle and memory)
+            self.h, self.stream, self.workspace, self._owned = _view[0], _view[1], None, False
+            return
+        import torch
+        self._owned = True
         self.workspace = torch.empty(workspace_bytes(p), dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
         h = C.c_void_p()
@@ -202,8 +218,73 @@ class System:
         return v.value
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and getattr(self, "_owned", True):
             self._lib.ec_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_workspace_bytes(ps):
+    arr = (Params * len(ps))(*ps)
+    n = C.c_size_t()
+    _check(load_library().ec_batch_workspace_bytes(arr, len(ps), C.byref(n)),
+           what="ec_batch_workspace_bytes")
+    return n.value
+
+
+class Batch:
+    """Several walled systems advanced by shared launches (one per sweep step).
+
+    systems[i] is a System view for per-system queries; the batch owns the
+    workspace (torch uint8 tensor) and, unless given, a stream of its own (a
+    HIP graph cannot be captured on the null stream).
+    """
+
+    def __init__(self, ps, device="cuda", stream=None):
+        import torch
+        self._lib = load_library()
+        self.ps = list(ps)
+        self._arr = (Params * len(self.ps))(*self.ps)
+        self.workspace = torch.empty(batch_workspace_bytes(self.ps), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.workspace.device)
+        h = C.c_void_p()
+        _check(self._lib.ec_init_batch(self._arr, len(self.ps), C.c_void_p(self.workspace.data_ptr()),
+                                       self.workspace.numel(), C.c_void_p(self.stream.cuda_stream),
+                                       C.byref(h)), None, "ec_init_batch")
+        self.h = h
+        self.systems = []
+        for i, p in enumerate(self.ps):
+            v = C.c_void_p()
+            _check(self._lib.ec_batch_system(self.h, i, C.byref(v)), self.h, "ec_batch_system", True)
+            self.systems.append(System(p, _view=(v, self.stream)))
+
+    def sweep(self, n_sweeps=1):
+        _check(self._lib.ec_sweep_batch(self.h, int(n_sweeps)), self.h, "ec_sweep_batch", True)
+
+    def set_graph(self, on):
+        _check(self._lib.ec_batch_set_graph(self.h, 1 if on else 0), self.h, "ec_batch_set_graph", True)
+
+    def set_cells_per_block(self, cpb):
+        _check(self._lib.ec_batch_set_cells_per_block(self.h, int(cpb)), self.h,
+               "ec_batch_set_cells_per_block", True)
+
+    def autotune(self, trial_sweeps=2):
+        cpb = C.c_int32()
+        ms = (C.c_double * 3)()
+        _check(self._lib.ec_batch_autotune(self.h, int(trial_sweeps), C.byref(cpb), ms), self.h,
+               "ec_batch_autotune", True)
+        return cpb.value, {1: ms[0], 2: ms[1], 4: ms[2]}
+
+    def close(self):
+        if getattr(self, "h", None):
+            for s in getattr(self, "systems", []):
+                s.h = None
+            self._lib.ec_destroy_batch(self.h)
             self.h = None
 
     def __del__(self):

@@ -80,3 +80,31 @@ def test_init_rejects_small_workspace_without_touching_gpu():
     assert st == E.EC_E_NOMEM and not h.value
     st = lib.ec_init_system(C.byref(p), None, 1 << 30, None, C.byref(h))
     assert st == E.EC_E_INVALID
+
+
+def test_batch_workspace_is_systems_plus_snapshot():
+    from tests import inputs
+    cfgs = inputs.batch_systems(64, seed=0)
+    ps = [P.make_params(c["n"], c["eta"], c["ell"], c["cells"], seed=c["seed"], system=i)
+          for i, c in enumerate(cfgs)]
+    solo = sum(P.workspace_bytes(p) for p in ps)
+    total = P.batch_workspace_bytes(ps)
+    assert 2 * solo <= total <= 2 * solo + 64 * 2 * 256 + 64 * 1024 + 4096
+
+
+def test_batch_rejects_periodic_systems_and_empty_batches():
+    good = P.make_params(65536, 0.70, 20.0, 16)
+    with pytest.raises(E.ECError) as ei:
+        P.batch_workspace_bytes([good, P.make_params(256, 0.70, 20.0, 1, dir_mode=E.EC_DIR_XY)])
+    assert ei.value.status == E.EC_E_UNSUPPORTED
+    lib = P.load_library()
+    n = C.c_size_t()
+    assert lib.ec_batch_workspace_bytes(C.byref(good), 0, C.byref(n)) == E.EC_E_INVALID
+
+
+def test_batch_init_rejects_small_workspace_without_touching_gpu():
+    lib = P.load_library()
+    ps = (E.Params * 2)(P.make_params(65536, 0.70, 20.0, 16), P.make_params(4096, 0.5, 20.0, 8))
+    h = C.c_void_p()
+    st = lib.ec_init_batch(ps, 2, C.c_void_p(0x1000), 16, None, C.byref(h))
+    assert st == E.EC_E_NOMEM and not h.value
