@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--workload", default="pec_1m")
     ap.add_argument("--cells-per-block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=("fp64", "fp32-screen"), default="fp64",
+                    help="fp32-screen: FP32 screening of candidates, FP64 for the survivors "
+                         "and every commit (identical events)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -104,8 +107,9 @@ def main():
         return bench_batch(args, torch, P)
     w = dict(inputs.WORKLOADS[args.workload])
     torch.cuda.set_device(0)
+    prec = P.EC_PREC_FP64 if args.precision == "fp64" else P.EC_PREC_FP32_SCREEN
     p = P.make_params(w["n"], w["eta"], w["ell"], w["cells"], dir_mode=w["dir_mode"],
-                      seed=w["seed"], cells_per_block=args.cells_per_block)
+                      seed=w["seed"], cells_per_block=args.cells_per_block, precision=prec)
     g = P.System(p, device="cuda:0")
     if args.copy_probe_mb > 0:
         nbytes = args.copy_probe_mb << 20
@@ -160,7 +164,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_disks": w["n"], "eta": w["eta"],
                    "cells_per_side": w["cells"], "ell": w["ell"], "directions": "isotropic",
-                   "precision": "fp64", "start": "lattice", "sweeps_before_timing": args.warmup},
+                   "precision": args.precision, "start": "lattice", "sweeps_before_timing": args.warmup},
         "sweeps_per_s": sweeps_s,
         "events_per_s": events / secs,
         "counts": counts,

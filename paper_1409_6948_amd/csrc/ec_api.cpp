@@ -108,13 +108,17 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
     int32_t cpb = p->cells_per_block == 0 ? 1 : p->cells_per_block;
     if (cpb != 1 && cpb != 2 && cpb != 4) { *why = "cells_per_block must be 0, 1, 2 or 4"; return EC_E_INVALID; }
     out->cpb = cpb;
-    out->lds_per_cell = ec::cell_lds_layout(nb + 2, out->cap_own).bytes;
+    out->lds_per_cell =
+        ec::cell_lds_layout(nb + 2, out->cap_own, p->precision == EC_PREC_FP32_SCREEN).bytes;
     if ((size_t)cpb * out->lds_per_cell > 160 * 1024) {
       *why = "LDS per workgroup exceeds 160 KiB"; return EC_E_UNSUPPORTED;
     }
   }
-  if (p->precision == EC_PREC_FP32_SCREEN) {
-    *why = "FP32 screening is not built yet"; return EC_E_UNSUPPORTED;
+  if (p->precision == EC_PREC_FP32_SCREEN && C == 1) {
+    *why = "FP32 screening is built for walled cells"; return EC_E_UNSUPPORTED;
+  }
+  if (!(p->screen_margin >= 0.0) || p->screen_margin > 1e-2) {
+    *why = "screen_margin must be in [0, 1e-2]"; return EC_E_INVALID;
   }
   // lattice start: k = ceil(sqrt(N)) columns, spacing L/k must exceed sigma
   int64_t k = (int64_t)std::ceil(std::sqrt((double)p->n_disks));
@@ -206,6 +210,7 @@ ec::LaunchShape shape_of(const ec::Dev& d, const ec_params& p) {
   sh.n_sys = 1;
   sh.periodic = d.C == 1;
   sh.any_distinct = d.start_mode == 1;
+  sh.fp32_screen = d.precision == EC_PREC_FP32_SCREEN;
   sh.max_n = d.n;
   sh.max_chains = d.chains_per_cell > 0 ? (int64_t)d.C * d.C * d.chains_per_cell : d.n;
   sh.max_cells = d.C * d.C;
@@ -214,6 +219,28 @@ ec::LaunchShape shape_of(const ec::Dev& d, const ec_params& p) {
   sh.max_lds_per_cell = d.lds_per_cell;
   (void)p;
   return sh;
+}
+
+// Error bounds of the FP32 screen.  With u = 2^-24, coordinates of staged
+// disks bounded by X = w + 2 sigma and window offsets by R = 6b, the FP32
+// offsets are within u (2X + R) of the exact ones, so a = r.d and c = r x d
+// are within Ea = u (4X + 8R) (also covering the FP64 values), sigma^2 - c^2
+// within Ed = 2 (sigma + Ea) Ea + 4 u sigma^2, and where the FP32
+// sigma^2 - c^2 exceeds Dg = sigma^2 / 64 its square root is within
+// Ed / sqrt(Dg - Ed) + 2 u sigma.  Each bound is doubled; the caller's
+// relative margin (times sigma) is added to the distance bound.
+void screen_bounds(ec::Dev* d) {
+  const double u = std::ldexp(1.0, -24);
+  const double sg = d->sigma, X = d->w + 2.0 * sg, R = 6.0 * d->b;
+  const double ea = 2.0 * u * (4.0 * X + 8.0 * R);
+  const double ed = 2.0 * (2.0 * (sg + ea) * ea + 4.0 * u * sg * sg);
+  const double dg = sg * sg / 64.0;
+  const double es = 2.0 * (ed / std::sqrt(dg - ed) + 2.0 * u * sg);
+  const double e = ea + es + 4.0 * u * (R + sg) + d->margin * sg;
+  d->scr_ea = (float)ea;
+  d->scr_ed = (float)ed;
+  d->scr_dg = (float)dg;
+  d->scr_e = (float)e;
 }
 
 // Create a system in a workspace region (validated parameters); with a
@@ -268,12 +295,13 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   d.gridb = dv.nb + 2;
   d.b = dv.nb > 0 ? dv.w / (double)dv.nb : 0.0;
   d.inv_b = dv.nb > 0 ? 1.0 / d.b : 0.0;
-  d.margin = p->screen_margin > 0.0 ? p->screen_margin : 1e-5;
+  d.margin = p->screen_margin > 0.0 ? p->screen_margin : 1e-5;  // relative to sigma
   d.cap_own = dv.cap_own;
   d.chains_per_cell = p->chains_per_cell;
   d.dir_mode = p->dir_mode;
   d.start_mode = p->start_mode;
   d.precision = p->precision;
+  if (p->precision == EC_PREC_FP32_SCREEN) screen_bounds(&d);
   d.lds_per_cell = dv.lds_per_cell;
   d.cells_per_block = dv.cpb;
   d.seed = p->seed;
@@ -558,6 +586,9 @@ ec_status batch_layout(const ec_params* ps, int32_t n, BatchLayout* bl, std::vec
     ec_status st = validate(&ps[i], &(*dvs)[(size_t)i], why);
     if (st != EC_OK) return st;
     if (ps[i].cells_per_side == 1) { *why = "batches hold walled systems (C >= 4) only"; return EC_E_UNSUPPORTED; }
+    if (ps[i].precision != ps[0].precision) {
+      *why = "the systems of a batch share one precision"; return EC_E_UNSUPPORTED;
+    }
     bl->off[(size_t)i] = o;
     o = align256(o + make_layout(ps[i].n_disks, ps[i].cells_per_side, ps[i].chains_per_cell).total);
   }
@@ -666,6 +697,7 @@ ec_status ec_init_batch(const ec_params* ps, int32_t n_sys, void* ws, size_t ws_
   std::memset(&sh, 0, sizeof sh);
   sh.n_sys = n_sys;
   sh.periodic = false;
+  sh.fp32_screen = ps[0].precision == EC_PREC_FP32_SCREEN;
   sh.cpb = 1;
   for (int32_t i = 0; i < n_sys; ++i) {
     ec_params p = ps[i];

@@ -67,6 +67,10 @@ struct Dev {
 
   int64_t n;
   double sigma, sig2, ell, L, half_L, w, cap, b, inv_b, margin;
+  // FP32 screen (precision 1): error bounds of the FP32 contact terms against
+  // the FP64 ones (a, sigma^2 - c^2, distance) and the threshold of
+  // sigma^2 - c^2 above which the FP32 distance is within scr_e
+  float scr_ea, scr_ed, scr_dg, scr_e;
   int32_t C, nb, gridb, cap_own, chains_per_cell, dir_mode, start_mode, precision;
   int32_t lds_per_cell, cells_per_block;
   int32_t search;                   // 0: 4x4-bin window with guard; 1: scan of every slot
@@ -79,10 +83,11 @@ struct Dev {
 // then the own-disk tables and one sink slot per lane (a target for the
 // lanes that do not store when one lane writes a position).
 struct CellLds {
-  int32_t off_pos, off_meta, off_mask, off_own_gid, off_own_loc, off_tmp, off_sink, bytes;
+  int32_t off_pos, off_meta, off_mask, off_own_gid, off_own_loc, off_tmp, off_sink, off_pos32, bytes;
 };
 
-__host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own) {
+// fp32: also an FP32 copy of every slot's position (the screened form).
+__host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own, bool fp32) {
   CellLds l;
   int slots = gridb * gridb * 4;
   int o = 0;
@@ -94,6 +99,7 @@ __host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own) {
   l.off_tmp = o;      o += 4 * cap_own;
   o = (o + 15) & ~15;
   l.off_sink = o;     o += 16 * 64;
+  l.off_pos32 = o;    o += fp32 ? 8 * slots : 0;
   l.bytes = (o + 15) & ~15;
   return l;
 }
@@ -107,6 +113,7 @@ struct LaunchShape {
   int32_t n_sys;
   bool periodic;            // one periodic cell (single system only)
   bool any_distinct;        // some system uses the distinct-start control
+  bool fp32_screen;         // the FP32-screened phase kernel (same for all)
   int64_t max_n;            // disks
   int64_t max_chains;       // chains per sweep
   int32_t max_cells;        // C * C

@@ -523,6 +523,8 @@ __device__ __forceinline__ int32_t load_err(const Dev& d) {
   return __hip_atomic_load(d.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// PREC 0: FP64 contact distances; PREC 1: FP32 screen, FP64 for the survivors.
+template <int PREC>
 __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q) {
   const Dev d = ds[blockIdx.y];
   const int64_t sweep = *d.sweep_ctr;
@@ -543,7 +545,7 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
   const int gridb = d.gridb, nb = d.nb;
   const int nslots = gridb * gridb * 4;
 
-  const CellLds lay = cell_lds_layout(gridb, d.cap_own);
+  const CellLds lay = cell_lds_layout(gridb, d.cap_own, PREC == 1);
   unsigned char* base = lds_raw + (size_t)wave * d.lds_per_cell;
   double2* pos = (double2*)(base + lay.off_pos);
   uint64_t* meta = (uint64_t*)(base + lay.off_meta);
@@ -554,6 +556,8 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
   // per-lane sink slots: lanes other than 0 write here when lane 0 stores the
   // moved disk, so the store needs no change of the execution mask
   double2* const sink = (double2*)(base + lay.off_sink) + lane;
+  float2* pos32 = (float2*)(base + lay.off_pos32);  // PREC 1 only
+  float2* const sink32 = (float2*)sink;
 
   // ---- stage: own disks, sorted by id -----------------------------------
   const int start = d.cell_start[cell];
@@ -572,6 +576,8 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
   }
   const double2 nan2 = make_double2(__builtin_nan(""), __builtin_nan(""));
   for (int s = lane; s < nslots; s += 64) pos[s] = nan2;
+  if (PREC == 1)
+    for (int s = lane; s < nslots; s += 64) pos32[s] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
   for (int bi = lane; bi < gridb * gridb; bi += 64) mask[bi] = 0;
   wave_sync();
 
@@ -588,6 +594,7 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
     if (slot >= 4) { atomicOr(d.err, ERR_BIN_CAP); continue; }
     int s = bin * 4 + slot;
     pos[s] = make_double2(vx, vy);
+    if (PREC == 1) pos32[s] = make_float2((float)vx, (float)vy);
     meta[s] = ((uint64_t)(uint32_t)k << 32) | (uint32_t)g;
     own_loc[k] = s;
   }
@@ -615,6 +622,7 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
         if (slot >= 4) { atomicOr(d.err, ERR_BIN_CAP); continue; }
         int s = bin * 4 + slot;
         pos[s] = make_double2(vx, vy);
+        if (PREC == 1) pos32[s] = make_float2((float)vx, (float)vy);
         meta[s] = (0xFFFFFFFFull << 32) | ((uint32_t)g | kFrozenBit);
       }
     }
@@ -707,7 +715,30 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
 
       // -- contact distance of the disk in this lane's window slot
       double s = 0.0;
-      const bool valid = contact(p.x - ax, p.y - ay, dx, dy, sig2, s);
+      bool valid;
+      if (PREC == 0) {
+        valid = contact(p.x - ax, p.y - ay, dx, dy, sig2, s);
+      } else {
+        // FP32 screen: lanes whose FP32 terms prove the FP64 test fails drop
+        // out; lanes whose FP32 distance is certain to within scr_e of the
+        // FP64 one drop out when they cannot be the minimum; the rest (the
+        // survivors) get the FP64 distance.  The minimum over the survivors
+        // is then the FP64 minimum over the window.
+        const float2 q32 = pos32[wbase + loff];
+        const float rx = q32.x - (float)ax, ry = q32.y - (float)ay;
+        const float dx32 = (float)dx, dy32 = (float)dy;
+        const float a32 = fmaf(rx, dx32, ry * dy32);
+        const float c32 = fmaf(rx, dy32, -(ry * dx32));
+        const float disc32 = fmaf(-c32, c32, (float)sig2);
+        const bool maybe = a32 > -d.scr_ea && disc32 > -d.scr_ed;
+        const bool sure = a32 > d.scr_ea && disc32 > d.scr_dg;
+        const float s32 = fmaxf(a32 - __builtin_amdgcn_sqrtf(disc32), 0.0f);
+        const float hi = sure ? s32 + d.scr_e : INFINITY;
+        const float bound = __uint_as_float(wave_min_all(__float_as_uint(hi)));
+        const bool survivor = maybe && (!sure || s32 - d.scr_e <= bound);
+        valid = false;
+        if (survivor) valid = contact(p.x - ax, p.y - ay, dx, dy, sig2, s);
+      }
       const int wl = wave_argmin_all(s, (uint32_t)m & ~kFrozenBit, valid);
 
       // the nearest disk (read from lane 0 when there is none; it is then unused)
@@ -802,12 +833,20 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
       if (nbx == abx && nby == aby) {
         double2* const dst = (lane == 0) ? pos + a_loc : sink;
         *dst = make_double2(ax, ay);
+        if (PREC == 1) {
+          float2* const dst32 = (lane == 0) ? pos32 + a_loc : sink32;
+          *dst32 = make_float2((float)ax, (float)ay);
+        }
       } else {
         const int abin = aby * gridb + abx, nbin = nby * gridb + nbx;
         const int nm = uniform_i32(mask[nbin]);
         const int free_slot = __builtin_ctz((unsigned)(~nm & 0xF) | 0x10u);
         if (free_slot >= 4) {
-          if (lane == 0) { atomicOr(d.err, ERR_BIN_CAP); pos[a_loc] = make_double2(ax, ay); }
+          if (lane == 0) {
+            atomicOr(d.err, ERR_BIN_CAP);
+            pos[a_loc] = make_double2(ax, ay);
+            if (PREC == 1) pos32[a_loc] = make_float2((float)ax, (float)ay);
+          }
         } else {
           const int ns = nbin * 4 + free_slot;
           if (lane == 0) {
@@ -815,6 +854,10 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
             pos[a_loc] = nan2;
             mask[nbin] = nm | (1 << free_slot);
             pos[ns] = make_double2(ax, ay);
+            if (PREC == 1) {
+              pos32[a_loc] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+              pos32[ns] = make_float2((float)ax, (float)ay);
+            }
             meta[ns] = ((uint64_t)(uint32_t)a_lidx << 32) | a_gid;
             own_loc[a_lidx] = ns;
           }
@@ -1084,7 +1127,11 @@ hipError_t launch_zero_tallies(const Dev* ds, int32_t n_cells, hipStream_t st) {
 }
 
 hipError_t set_phase_lds_limit(int bytes) {
-  return hipFuncSetAttribute((const void*)k_phase, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  hipError_t e = hipFuncSetAttribute((const void*)k_phase<0>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_phase<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             bytes);
 }
 
 hipError_t launch_reduce(const Dev* ds, hipStream_t st) {
@@ -1097,9 +1144,9 @@ hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
   const unsigned ns = (unsigned)sh.n_sys;
   if (sh.periodic) {
     size_t lds = (size_t)sh.max_n * 16 + (size_t)sh.max_n * 4;
-    if (ev) hipEventRecord(ev->begin[0], st);
+    if (ev) (void)hipEventRecord(ev->begin[0], st);
     hipLaunchKernelGGL(k_periodic, dim3(1, ns), dim3(64), lds, st, ds);
-    if (ev) hipEventRecord(ev->end[0], st);
+    if (ev) (void)hipEventRecord(ev->end[0], st);
     hipLaunchKernelGGL(k_sweep_done, dim3(1, ns), dim3(64), 0, st, ds);
     return hipGetLastError();
   }
@@ -1117,9 +1164,12 @@ hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
   const unsigned grid = (unsigned)((sh.max_active + cpb - 1) / cpb);
   const size_t lds = (size_t)cpb * sh.max_lds_per_cell;
   for (int q = 0; q < 4; ++q) {
-    if (ev) hipEventRecord(ev->begin[q], st);
-    hipLaunchKernelGGL(k_phase, dim3(grid, ns), dim3(64 * cpb), lds, st, ds, q);
-    if (ev) hipEventRecord(ev->end[q], st);
+    if (ev) (void)hipEventRecord(ev->begin[q], st);
+    if (sh.fp32_screen)
+      hipLaunchKernelGGL(k_phase<1>, dim3(grid, ns), dim3(64 * cpb), lds, st, ds, q);
+    else
+      hipLaunchKernelGGL(k_phase<0>, dim3(grid, ns), dim3(64 * cpb), lds, st, ds, q);
+    if (ev) (void)hipEventRecord(ev->end[q], st);
   }
   hipLaunchKernelGGL(k_sweep_done, dim3(1, ns), dim3(64), 0, st, ds);
   return hipGetLastError();

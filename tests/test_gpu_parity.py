@@ -35,10 +35,10 @@ def P():
 
 
 def _gpu_system(P, n, eta, ell, cells, dir_mode, seed=1, chains_per_cell=0, start_mode=0,
-                cells_per_block=0, flags=0):
+                cells_per_block=0, flags=0, precision=0):
     p = P.make_params(n, eta, ell, cells, dir_mode=dir_mode, seed=seed,
                       chains_per_cell=chains_per_cell, start_mode=start_mode,
-                      cells_per_block=cells_per_block, flags=flags)
+                      cells_per_block=cells_per_block, flags=flags, precision=precision)
     return P.System(p)
 
 
@@ -50,13 +50,13 @@ def _oracle_state(n, eta, ell, cells, dir_mode, seed=1, chains_per_cell=0, start
 
 
 def _compare_full(P, n, eta, ell, cells, dir_mode, sweeps, seed=1, chains_per_cell=0,
-                  start_mode=0, x=None, y=None, cells_per_block=0, flags=0):
+                  start_mode=0, x=None, y=None, cells_per_block=0, flags=0, precision=0):
     _say(f"[parity] n={n} eta={eta} ell={ell} C={cells} dir={dir_mode} sweeps={sweeps} "
          f"seed={seed} n_m={chains_per_cell} start={start_mode} cpb={cells_per_block} "
-         f"flags={flags}")
+         f"flags={flags} precision={precision}")
     st = _oracle_state(n, eta, ell, cells, dir_mode, seed, chains_per_cell, start_mode, x, y)
     g = _gpu_system(P, n, eta, ell, cells, dir_mode, seed, chains_per_cell, start_mode,
-                    cells_per_block, flags)
+                    cells_per_block, flags, precision)
     gx, gy = g.get_positions()
     if x is None:
         np.testing.assert_array_equal(gx, st.x)  # the two start lattices agree bit for bit
@@ -224,3 +224,35 @@ def test_full_size_first_phase_cells(P, name):
     if n <= 1 << 20:
         _say(f"[full-size] {name}: overlap check")
         assert _min_distance_grid(gx, gy, L) > 1.0 - 1e-12
+
+
+# ---------------------------------------------------------------------------
+# FP32-screened form: the same events as the FP64 form, hence as the oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,eta,cells,ell,sweeps", [
+    (4096, 0.72, 8, 20.0, 3),
+    (4096, 0.30, 8, 20.0, 3),
+    (2304, 0.65, 6, 12.0, 2),
+])
+def test_fp32_screen_matches_oracle(P, n, eta, cells, ell, sweeps):
+    _compare_full(P, n, eta, ell, cells, 1, sweeps, precision=1)
+
+
+def test_fp32_screen_equals_fp64_at_full_size(P):
+    """1M disks, eta 0.72, 64 x 64 cells: positions and per-sweep digests of the
+    screened form equal those of the FP64 form over several sweeps."""
+    w = inputs.WORKLOADS["pec_1m"]
+    sweeps = 3
+    _say(f"[fp32] pec_1m: {sweeps} sweeps in each precision")
+    out = []
+    for prec in (0, 1):
+        g = _gpu_system(P, w["n"], w["eta"], w["ell"], w["cells"], 1, seed=w["seed"],
+                        precision=prec)
+        g.sweep(sweeps)
+        x, y = g.get_positions()
+        out.append((x, y, g.get_digests(sweeps), g.measure_pressure()[2]))
+        g.close()
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    np.testing.assert_array_equal(out[0][2], out[1][2])
+    assert out[0][3] == out[1][3]
