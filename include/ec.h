@@ -129,6 +129,19 @@ ec_status ec_sweep(ec_system sys, int64_t n_sweeps);
  * per chain, draw retries; ec_last_error names the first tripped chain). */
 ec_status ec_measure_pressure(ec_system sys, double* z, double* beta_p_sigma2, uint64_t* counts);
 
+/* Hexatic order parameter of the current positions, eq. (Psi) of Sec. 2:
+ * Psi = N^-1 sum_k Psi_k, Psi_k = n_k^-1 sum_l exp(6 i phi_kl) with phi_kl the
+ * angle of the bond k -> l against the x axis.  Neighbours are all disks
+ * within r_cut (minimum image), not the Delaunay neighbours of the paper;
+ * r_cut <= 0 selects 1.4 sigma, and r_cut may not exceed the cell side (half
+ * the box with C = 1; EC_E_INVALID).  A disk without neighbours has Psi_k = 0.
+ * per_disk (may be NULL): 2N doubles, re and im of each Psi_k in disk-id
+ * order.  mean_neighbours (may be NULL): mean n_k.  Bond terms are summed per
+ * disk in units of 2^-52 and the disks in a fixed order, so results repeat
+ * bit for bit.  Synchronises. */
+ec_status ec_measure_psi6(ec_system sys, double r_cut, double* psi_re, double* psi_im,
+                          double* mean_neighbours, double* per_disk);
+
 /* Clear the pressure tallies (asynchronous). */
 ec_status ec_reset_tallies(ec_system sys);
 

@@ -647,3 +647,43 @@ int orc_run_cells(const orc_params* p, double* x, double* y, int64_t sweep, int3
   sweep_cells(p, x, y, sweep, n_phases, cells, n_cells, acc_delta, acc_cnt, NULL, cell_digest);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Hexatic order parameter (Sec. 2, eq. Psi), cutoff neighbours               */
+/* ------------------------------------------------------------------------ */
+void orc_psi6_box(int64_t n, double L, const double* x, const double* y, double r_cut,
+                  double* re, double* im, double* mean_nb, double* per_disk) {
+  const double half = 0.5 * L, rc2 = r_cut * r_cut;
+  double sre = 0.0, sim = 0.0, snb = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    double kre = 0.0, kim = 0.0;
+    int64_t nk = 0;
+    for (int64_t l = 0; l < n; ++l) {
+      if (l == k) continue;
+      double dx = x[l] - x[k], dy = y[l] - y[k];
+      if (dx < -half) dx += L; else if (dx >= half) dx -= L;
+      if (dy < -half) dy += L; else if (dy >= half) dy -= L;
+      const double r2 = dx * dx + dy * dy;
+      if (!(r2 < rc2)) continue;
+      /* exp(6 i phi) = ((dx + i dy) / r)^6 */
+      const double phi = atan2(dy, dx);
+      kre += cos(6.0 * phi);
+      kim += sin(6.0 * phi);
+      nk += 1;
+    }
+    if (nk > 0) { kre /= (double)nk; kim /= (double)nk; }
+    if (per_disk) { per_disk[2 * k] = kre; per_disk[2 * k + 1] = kim; }
+    sre += kre;
+    sim += kim;
+    snb += (double)nk;
+  }
+  if (re) *re = n > 0 ? sre / (double)n : 0.0;
+  if (im) *im = n > 0 ? sim / (double)n : 0.0;
+  if (mean_nb) *mean_nb = n > 0 ? snb / (double)n : 0.0;
+}
+
+void orc_psi6(const orc_params* p, const double* x, const double* y, double r_cut, double* re,
+              double* im, double* mean_nb, double* per_disk) {
+  orc_psi6_box(p->n, orc_box_length(p->n, p->sigma, p->eta), x, y, r_cut, re, im, mean_nb,
+               per_disk);
+}

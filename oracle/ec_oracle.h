@@ -98,6 +98,21 @@ int      orc_run_cells(const orc_params* p, double* x, double* y, int64_t sweep,
                        const int32_t* cells, int32_t n_cells, double* acc_delta, uint64_t* acc_cnt,
                        uint64_t* cell_digest);
 
+/*
+ * Hexatic order parameter, eq. (Psi) of Sec. 2: Psi = N^-1 sum_k Psi_k with
+ * Psi_k = n_k^-1 sum_l exp(6 i phi_kl), phi_kl the angle of the vector from k
+ * to neighbour l against the x axis.  Neighbours: every other disk within
+ * r_cut (minimum image in the L x L box of p), in place of the Delaunay
+ * neighbours of the paper; a disk without neighbours has Psi_k = 0.  Brute
+ * force over all pairs.  per_disk (may be NULL) receives re, im of each
+ * Psi_k (2N doubles); mean_nb (may be NULL) the mean neighbour count.
+ */
+void     orc_psi6(const orc_params* p, const double* x, const double* y, double r_cut,
+                  double* re, double* im, double* mean_nb, double* per_disk);
+/* The same over positions in an explicit periodic box of side L. */
+void     orc_psi6_box(int64_t n, double L, const double* x, const double* y, double r_cut,
+                      double* re, double* im, double* mean_nb, double* per_disk);
+
 /* Event log: set a buffer before orc_run; events beyond capacity are counted but dropped. */
 void     orc_set_log(orc_event* buf, int64_t capacity);
 int64_t  orc_log_count(void);

@@ -62,6 +62,8 @@ def lib():
         L.orc_run_cells.restype = C.c_int
         L.orc_run_cells.argtypes = [pp, dp, dp, C.c_int64, C.c_int32, i32p, C.c_int32, dp, u64p,
                                     u64p]
+        L.orc_psi6.argtypes = [pp, dp, dp, C.c_double, dp, dp, dp, dp]
+        L.orc_psi6_box.argtypes = [C.c_int64, C.c_double, dp, dp, C.c_double, dp, dp, dp, dp]
         L.orc_set_log.argtypes = [C.POINTER(Event), C.c_int64]
         L.orc_log_count.restype = C.c_int64
         _lib = L
@@ -180,6 +182,25 @@ class State:
         z = 1.0 + s / (chains * self.p.ell)
         L = box_length(self.p.n, self.p.sigma, self.p.eta)
         return z, z * self.p.n * self.p.sigma ** 2 / (L * L)
+
+
+def psi6_box(n, L, x, y, r_cut=1.4):
+    """Hexatic order parameter (Sec. 2, eq. Psi) with cutoff neighbours in a
+    periodic L x L box: returns (Psi as complex, mean neighbour count,
+    per-disk Psi_k as a complex array)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    re, im, nb = C.c_double(), C.c_double(), C.c_double()
+    per = np.zeros(2 * int(n), dtype=np.float64)
+    dp = C.POINTER(C.c_double)
+    lib().orc_psi6_box(int(n), float(L), x.ctypes.data_as(dp), y.ctypes.data_as(dp), float(r_cut),
+                       C.byref(re), C.byref(im), C.byref(nb), per.ctypes.data_as(dp))
+    return complex(re.value, im.value), nb.value, per[0::2] + 1j * per[1::2]
+
+
+def psi6(p, x, y, r_cut=1.4):
+    """psi6_box in the box of the parameters p."""
+    return psi6_box(p.n, box_length(p.n, p.sigma, p.eta), x, y, r_cut)
 
 
 def run_logged(p, x, y, sweep0, n_sweeps, capacity=1 << 20):

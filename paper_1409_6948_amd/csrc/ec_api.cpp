@@ -20,7 +20,8 @@ constexpr double kPi = 3.14159265358979323846;
 
 struct Layout {
   size_t dev, sweep_ctr, x, y, cell_of, cell_ids, cell_count, cell_fill, cell_start, acc_delta, acc_cnt,
-      ring, cell_digest, draws, err, red, chain_start, chain_dir, shuffle, dbg, total;
+      ring, cell_digest, draws, err, red, chain_start, chain_dir, shuffle, dbg, psi, psi_part, psi_red,
+      total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -51,6 +52,9 @@ Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell) {
   l.chain_dir = o;  o = align256(o + 16 * max_chains);
   l.shuffle = o;    o = align256(o + (C == 1 ? 0 : 4 * (size_t)n));
   l.dbg = o;        o = align256(o + 8 * ec::kDebugWords);
+  l.psi = o;        o = align256(o + 16 * (size_t)n);
+  l.psi_part = o;   o = align256(o + 24 * (((size_t)n + 255) / 256));
+  l.psi_red = o;    o = align256(o + 32);
   l.total = o;
   return l;
 }
@@ -281,6 +285,9 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   d.shuffle = (int32_t*)(b + lay.shuffle);
   d.dbg = (double*)(b + lay.dbg);
   d.sweep_ctr = (int64_t*)(b + lay.sweep_ctr);
+  d.psi = (double2*)(b + lay.psi);
+  d.psi_part = (double*)(b + lay.psi_part);
+  d.psi_red = (double*)(b + lay.psi_red);
   d.search = (p->flags & EC_FLAG_SCAN_SEARCH) ? 1 : 0;
   d.n = p->n_disks;
   d.sigma = p->sigma;
@@ -431,6 +438,29 @@ ec_status ec_measure_pressure(ec_system s, double* z, double* bp, uint64_t* coun
   if (z) *z = zz;
   if (bp) *bp = zz * (double)s->p.n_disks * s->p.sigma * s->p.sigma / (s->dv.L * s->dv.L);
   if (counts) for (int k = 0; k < ec::CNT_NCOL; ++k) counts[k] = cnt[k];
+  return EC_OK;
+}
+
+ec_status ec_measure_psi6(ec_system s, double r_cut, double* psi_re, double* psi_im,
+                          double* mean_neighbours, double* per_disk) {
+  if (!s) return EC_E_INVALID;
+  const double rc = r_cut > 0.0 ? r_cut : 1.4 * s->p.sigma;
+  const double limit = s->p.cells_per_side == 1 ? 0.5 * s->dv.L : s->dv.w;
+  if (!(rc <= limit)) {
+    s->last_error = "r_cut must not exceed the cell side (half the box for one periodic cell)";
+    return EC_E_INVALID;
+  }
+  EC_HIP(s, ec::launch_psi6(s->dev_d, s->shape, rc, s->stream));
+  double red[3];
+  EC_HIP(s, hipMemcpyAsync(red, s->dev.psi_red, sizeof red, hipMemcpyDeviceToHost, s->stream));
+  if (per_disk)
+    EC_HIP(s, hipMemcpyAsync(per_disk, s->dev.psi, 16 * (size_t)s->p.n_disks, hipMemcpyDeviceToHost,
+                             s->stream));
+  ec_status st = check_err(s);
+  if (st != EC_OK) return st;
+  if (psi_re) *psi_re = red[0];
+  if (psi_im) *psi_im = red[1];
+  if (mean_neighbours) *mean_neighbours = red[2];
   return EC_OK;
 }
 

@@ -64,6 +64,9 @@ struct Dev {
   int32_t* shuffle;                 // [N] per-cell shuffled lists (distinct-start mode)
   double* dbg;                      // [kDebugWords] state of the first wave that tripped a cap
   int64_t* sweep_ctr;               // [1] sweeps done; read by every kernel of a sweep
+  double2* psi;                     // [N] per-disk hexatic order Psi_k (re, im)
+  double* psi_part;                 // [3 * ceil(N/256)] per-block sums (re, im, neighbours)
+  double* psi_red;                  // [3] Psi (re, im) and the mean neighbour count
 
   int64_t n;
   double sigma, sig2, ell, L, half_L, w, cap, b, inv_b, margin;
@@ -137,5 +140,9 @@ hipError_t launch_reduce(const Dev* ds, hipStream_t st);
 // Allow the phase kernel up to `bytes` of dynamic LDS per workgroup.
 hipError_t set_phase_lds_limit(int bytes);
 hipError_t launch_zero_tallies(const Dev* ds, int32_t n_cells, hipStream_t st);
+// Hexatic order parameter of one system (cutoff neighbours within r_cut,
+// r_cut <= cell side): rebin of the current sweep, per-disk Psi_k, and a
+// fixed-order reduction into psi_red.
+hipError_t launch_psi6(const Dev* ds, const LaunchShape& sh, double r_cut, hipStream_t st);
 
 }  // namespace ec

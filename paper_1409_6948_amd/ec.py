@@ -27,7 +27,7 @@ EXPORTED = ("ec_workspace_bytes", "ec_init_system", "ec_sweep", "ec_measure_pres
             "ec_set_timing", "ec_get_timing", "ec_destroy", "ec_status_string",
             "ec_last_error", "ec_batch_workspace_bytes", "ec_init_batch", "ec_sweep_batch",
             "ec_batch_system", "ec_batch_set_graph", "ec_batch_set_cells_per_block",
-            "ec_batch_autotune", "ec_batch_last_error", "ec_destroy_batch")
+            "ec_batch_autotune", "ec_batch_last_error", "ec_destroy_batch", "ec_measure_psi6")
 
 
 class ECError(RuntimeError):
@@ -68,6 +68,7 @@ def load_library():
         "ec_init_system": [P, vp, C.c_size_t, vp, C.POINTER(vp)],
         "ec_sweep": [vp, C.c_int64],
         "ec_measure_pressure": [vp, dp, dp, u64p],
+        "ec_measure_psi6": [vp, C.c_double, dp, dp, dp, dp],
         "ec_reset_tallies": [vp],
         "ec_get_positions": [vp, dp, dp, C.c_int64],
         "ec_set_positions": [vp, dp, dp, C.c_int64],
@@ -165,6 +166,17 @@ class System:
                                              cnt.ctypes.data_as(C.POINTER(C.c_uint64))),
                self.h, "ec_measure_pressure")
         return z.value, bp.value, dict(zip(COUNT_NAMES, (int(v) for v in cnt)))
+
+    def measure_psi6(self, r_cut=0.0, per_disk=False):
+        """Hexatic order parameter with cutoff neighbours: (Psi, mean neighbour
+        count[, per-disk Psi_k as a complex array])."""
+        re, im, nb = C.c_double(), C.c_double(), C.c_double()
+        per = np.zeros(2 * self.n, dtype=np.float64) if per_disk else None
+        _check(self._lib.ec_measure_psi6(self.h, float(r_cut), C.byref(re), C.byref(im), C.byref(nb),
+                                         _dptr(per) if per_disk else None),
+               self.h, "ec_measure_psi6")
+        out = (complex(re.value, im.value), nb.value)
+        return out + (per[0::2] + 1j * per[1::2],) if per_disk else out
 
     def reset_tallies(self):
         _check(self._lib.ec_reset_tallies(self.h), self.h, "ec_reset_tallies")

@@ -481,3 +481,55 @@ def test_low_density_virial_series(cells):
     assert e < 3e-4
     if cells > 1:
         assert st.acc_cnt[:, O.CNT_FROZEN].sum() > 0.02 * st.acc_cnt[:, O.CNT_LIFTS].sum()
+
+
+# ---------------------------------------------------------------------------
+# Hexatic order parameter (Sec. 2, eq. Psi) with cutoff neighbours
+# ---------------------------------------------------------------------------
+def test_psi6_start_lattice_closed_form():
+    """Centred-rectangular start lattice (spacing a, odd rows shifted a/2):
+    every disk has 2 neighbours at 0 and 180 degrees and 4 at +-atan2(1, 1/2)
+    (+180), all within 1.4 sigma, so Psi_k = (2 + 4 cos(6 atan2(1, 1/2))) / 6."""
+    p = O.params(4096, 0.72, 20.0, 8)
+    x, y = O.lattice(p)
+    psi, nb, per = O.psi6(p, x, y, 1.4)
+    want = (2.0 + 4.0 * math.cos(6.0 * math.atan2(1.0, 0.5))) / 6.0
+    assert nb == 6.0
+    assert abs(psi - want) < 1e-12
+    assert np.max(np.abs(per - want)) < 1e-12
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.1, 0.37, -0.8])
+def test_psi6_rotated_triangular_patch(theta):
+    """Interior disks of a triangular patch rotated by theta: Psi_k = exp(6 i theta)."""
+    a = 1.1
+    pts = []
+    for j in range(-4, 5):
+        for i in range(-4, 5):
+            px, py = (i + 0.5 * j) * a, j * a * math.sqrt(3.0) / 2.0
+            pts.append((px * math.cos(theta) - py * math.sin(theta) + 50.0,
+                        px * math.sin(theta) + py * math.cos(theta) + 50.0))
+    pts = np.array(pts)
+    _, _, per = O.psi6_box(len(pts), 100.0, pts[:, 0], pts[:, 1], 1.4)
+    centre = 4 * 9 + 4
+    assert abs(per[centre] - complex(math.cos(6 * theta), math.sin(6 * theta))) < 1e-12
+    inner = [j * 9 + i for j in range(2, 7) for i in range(2, 7)]
+    assert np.max(np.abs(per[inner] - complex(math.cos(6 * theta), math.sin(6 * theta)))) < 1e-12
+
+
+def test_psi6_pair_isolated_disk_and_periodic_image():
+    """A pair at angle alpha: both disks have Psi_k = exp(6 i alpha) (the bond
+    reversed adds 6 pi); a lone disk has Psi_k = 0; a pair across the periodic
+    boundary is found through the minimum image."""
+    alpha = 0.3
+    L = 20.0
+    x = np.array([5.0, 5.0 + 1.2 * math.cos(alpha), 15.0])
+    y = np.array([5.0, 5.0 + 1.2 * math.sin(alpha), 15.0])
+    psi, nb, per = O.psi6_box(3, L, x, y, 1.4)
+    e = complex(math.cos(6 * alpha), math.sin(6 * alpha))
+    assert abs(per[0] - e) < 1e-14 and abs(per[1] - e) < 1e-14 and per[2] == 0
+    assert abs(psi - 2 * e / 3) < 1e-14 and abs(nb - 2 / 3) < 1e-14
+    x2 = np.array([0.3, L - 0.5])
+    y2 = np.array([7.0, 7.0])
+    _, nb2, per2 = O.psi6_box(2, L, x2, y2, 1.4)
+    assert nb2 == 1.0 and abs(per2[0] - 1.0) < 1e-14 and abs(per2[1] - 1.0) < 1e-14
