@@ -203,11 +203,11 @@ __device__ __forceinline__ int wave_argmin_all(double s, uint32_t id, bool valid
   const uint64_t sb = (uint64_t)__double_as_longlong(s);
   const unsigned hi = valid ? (unsigned)(sb >> 32) : 0xFFFFFFFFu;
   const unsigned m = wave_min_all(hi);
-  uint64_t mask = __ballot(valid && hi == m);
+  uint64_t mask = __builtin_amdgcn_ballot_w64(valid && hi == m);
   if (mask == 0) return -1;
   int wl = __ffsll((unsigned long long)mask) - 1;
-  mask &= mask - 1;
-  if (mask) {  // equal high words: resolve on the full key
+  if (__popcll(mask) > 1) {  // equal high words: resolve on the full key
+    mask &= mask - 1;
     uint64_t bs = readlane_u64(sb, wl);
     uint32_t bi = (uint32_t)readlane_i32((int)id, wl);
     while (mask) {
@@ -660,11 +660,22 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
   int aborted = 0;
   int stop = 0;  // nonzero once a poll sees the device error word set
 
+  // draws of chain 0; later, those of chain k + 1 and the device error word
+  // are loaded while chain k runs (their latency is then hidden)
+  int32_t nxt_start = n_m > 0 ? d.chain_start[cbase] : 0;
+  double2 nxt_dir = n_m > 0 ? d.chain_dir[cbase] : make_double2(1.0, 0.0);
+  int32_t nxt_err = load_err(d);
   for (int64_t k = 0; k < n_m && aborted == 0; ++k) {
-    int j = uniform_i32(d.chain_start[cbase + k]);
+    int j = uniform_i32(nxt_start);
     if (j < 0 || j >= n_own) j = 0;  // guarded: the draw kernel writes indices below n_own
-    const double2 dir = d.chain_dir[cbase + k];
+    const double2 dir = nxt_dir;
     double dx = dir.x, dy = dir.y;
+    stop = uniform_i32(nxt_err);
+    if (k + 1 < n_m) {
+      nxt_start = d.chain_start[cbase + k + 1];
+      nxt_dir = d.chain_dir[cbase + k + 1];
+    }
+    nxt_err = load_err(d);
     // per-direction constants
     double idx, idy, wallx, wally, idxw, idyw, dsafe;
     int xneg, yneg;
@@ -704,7 +715,6 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
     double2 p = pos[wbase + loff];
     uint64_t m = meta[wbase + loff];
     int ended = 0;  // the chain length is used up
-    stop = uniform_i32(load_err(d));
 
     while (ended == 0 && stop == 0 && n_events < (int)kMaxEventsPerChain) {
       // walls of the cell: (wall - v) / d with 1/d precomputed, clamped at 0
@@ -772,10 +782,52 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
         const int by_ = min(max((int)(nay * inv_b) + 1, 1), nb);                    \
         bool ok_ = true;                                                            \
         if (CHECK_WINDOW) ok_ = step <= dsafe;                                      \
+        const int cr_ = (bx_ != abx || by_ != aby) ? 1 : 0;                          \
         packed = uniform_i32(bx_ | (by_ << 8) | (kd << 16) | ((en ? 1 : 0) << 20) | \
-                             ((ok_ ? 1 : 0) << 21));                                \
+                             ((ok_ ? 1 : 0) << 21) | (cr_ << 22));                  \
       } while (0)
       EC_DECIDE(true);
+      // the common event: a lift the window vouches for, with the moved disk
+      // staying in its bin and chain length left over
+      constexpr int kFastMask = (7 << 16) | (1 << 20) | (1 << 21) | (1 << 22);
+      constexpr int kFast = (EV_LIFT << 16) | (1 << 21);
+      if ((packed & kFastMask) == kFast) {
+        {
+          const uint64_t sb = (uint64_t)__double_as_longlong(step);
+          const uint32_t tag = ((uint32_t)EV_LIFT << 29) | (wgid & ~kFrozenBit);
+          const bool mine = lane == n_ring;
+          rec_lo = mine ? (uint32_t)sb : rec_lo;
+          rec_hi = mine ? (uint32_t)(sb >> 32) : rec_hi;
+          rec_tag = mine ? tag : rec_tag;
+        }
+        {
+          double2* const dst = (lane == 0) ? pos + a_loc : sink;
+          *dst = make_double2(nax, nay);
+          if (PREC == 1) {
+            float2* const dst32 = (lane == 0) ? pos32 + a_loc : sink32;
+            *dst32 = make_float2((float)nax, (float)nay);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (++n_ring == kDigestBatch) {
+          h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first);
+          ring_first += kDigestBatch;
+          n_ring = 0;
+        }
+        acc = acc + fma(wpx - nax, dx, (wpy - nay) * dy);
+        n_lift += 1;
+        rem = rem - e;
+        a_loc = w_slot;
+        a_gid = wgid;
+        a_lidx = w_lidx;
+        abx = w_bx;
+        aby = w_by;
+        ax = wpx;
+        ay = wpy;
+        EC_WINDOW(abx, aby, xneg, yneg);
+        p = pos[wbase + loff];
+        m = meta[wbase + loff];
+      } else {
       if (((packed >> 21) & 1) == 0) {
         // the window cannot vouch for this event: exact search over every slot
         double ls = INFINITY;
@@ -917,6 +969,7 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
       EC_WINDOW(abx, aby, xneg, yneg);
       p = pos[wbase + loff];
       m = meta[wbase + loff];
+      }
       // event cap and abort polling (every value here is wave-uniform)
       ++n_events;
       if ((n_events & ((int)kAbortPollEvents - 1)) == 0) stop = uniform_i32(load_err(d));
