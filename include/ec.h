@@ -142,6 +142,35 @@ ec_status ec_measure_pressure(ec_system sys, double* z, double* beta_p_sigma2, u
 ec_status ec_measure_psi6(ec_system sys, double r_cut, double* psi_re, double* psi_im,
                           double* mean_neighbours, double* per_disk);
 
+/* ---- Pressure from the pair correlation at contact, eq. (pressure) of Sec. 2:
+ * beta P sigma^2 = sigma^2 rho (1 + (pi/2) sigma^2 rho g(sigma+)).  Ordered pairs
+ * (k, l), k != l, are counted in bins [e_i, e_i+1), e_i = sigma + i delta,
+ * delta = (r_max - sigma)/n_bins, by the minimum-image distance
+ * d = sqrt(dx*dx + dy*dy), bin floor((d - sigma)/delta); integer counts, so the
+ * result does not depend on summation order. */
+
+/* Add the current configuration's pair counts to the system's histogram
+ * (asynchronous).  sigma < r_max <= cell side (half the box with C = 1),
+ * 1 <= n_bins <= 1024 (EC_E_INVALID).  A call with other r_max or n_bins than
+ * the series so far starts a new series. */
+ec_status ec_gr_accumulate(ec_system sys, double r_max, int32_t n_bins);
+
+/* Counts of the series (counts[n_bins]), the number of configurations added
+ * and the pairs closer than sigma (0 for a valid configuration).  Synchronises. */
+ec_status ec_gr_counts(ec_system sys, uint64_t* counts, int64_t* samples, uint64_t* overlaps);
+
+/* Clear the histogram (asynchronous). */
+ec_status ec_gr_reset(ec_system sys);
+
+/* Host only (no device call): g(R_i) = counts_i / (samples N rho pi (e_i+1^2 - e_i^2))
+ * with rho = N / box^2, at R_i = 2 (e_i+1^3 - e_i^3) / (3 (e_i+1^2 - e_i^2)); the
+ * contact value g(sigma+) from a least-squares quadratic in R - sigma over the
+ * bins with R_i - sigma < fit_width (at least 3); z = beta P / rho =
+ * 1 + (pi/2) sigma^2 rho g(sigma+).  g, R (n_bins each), g_contact, z may be NULL. */
+ec_status ec_gr_normalize(int64_t n_disks, double box, double sigma, double r_max, int32_t n_bins,
+                          const uint64_t* counts, int64_t samples, double fit_width, double* g,
+                          double* R, double* g_contact, double* z);
+
 /* Clear the pressure tallies (asynchronous). */
 ec_status ec_reset_tallies(ec_system sys);
 

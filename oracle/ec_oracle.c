@@ -687,3 +687,29 @@ void orc_psi6(const orc_params* p, const double* x, const double* y, double r_cu
   orc_psi6_box(p->n, orc_box_length(p->n, p->sigma, p->eta), x, y, r_cut, re, im, mean_nb,
                per_disk);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Pair histogram (pressure route of eq. pressure)                          */
+/* ------------------------------------------------------------------------ */
+void orc_pair_histogram(const orc_params* p, const double* x, const double* y, double r_max,
+                        int32_t n_bins, uint64_t* counts, uint64_t* overlaps) {
+  const double L = orc_box_length(p->n, p->sigma, p->eta), half = 0.5 * L;
+  const double delta = (r_max - p->sigma) / (double)n_bins;
+  for (int64_t k = 0; k < p->n; ++k) {
+    for (int64_t l = 0; l < p->n; ++l) {
+      if (l == k) continue;
+      double dx = x[l] - x[k], dy = y[l] - y[k];
+      if (dx < -half) dx += L; else if (dx >= half) dx -= L;
+      if (dy < -half) dy += L; else if (dy >= half) dy -= L;
+      const double d2 = dx * dx + dy * dy;
+      if (!(d2 < r_max * r_max)) continue;
+      const double dist = sqrt(d2);
+      if (dist < p->sigma) {
+        if (overlaps) *overlaps += 1;
+        continue;
+      }
+      const double t = floor((dist - p->sigma) / delta);
+      if (t < (double)n_bins) counts[(int64_t)t] += 1;
+    }
+  }
+}

@@ -113,6 +113,16 @@ void     orc_psi6(const orc_params* p, const double* x, const double* y, double 
 void     orc_psi6_box(int64_t n, double L, const double* x, const double* y, double r_cut,
                       double* re, double* im, double* mean_nb, double* per_disk);
 
+/*
+ * Pair histogram for the pressure route of eq. (pressure), Sec. 2: counts[i]
+ * += number of ordered pairs (k, l), k != l, whose minimum-image distance d
+ * (d^2 = dx*dx + dy*dy, d = sqrt(d^2)) lies in bin i = floor((d - sigma) /
+ * delta), delta = (r_max - sigma) / n_bins, for 0 <= i < n_bins.  Pairs closer
+ * than sigma are counted in *overlaps (may be NULL).  Brute force over all pairs.
+ */
+void     orc_pair_histogram(const orc_params* p, const double* x, const double* y, double r_max,
+                            int32_t n_bins, uint64_t* counts, uint64_t* overlaps);
+
 /* Event log: set a buffer before orc_run; events beyond capacity are counted but dropped. */
 void     orc_set_log(orc_event* buf, int64_t capacity);
 int64_t  orc_log_count(void);

@@ -64,6 +64,7 @@ def lib():
                                     u64p]
         L.orc_psi6.argtypes = [pp, dp, dp, C.c_double, dp, dp, dp, dp]
         L.orc_psi6_box.argtypes = [C.c_int64, C.c_double, dp, dp, C.c_double, dp, dp, dp, dp]
+        L.orc_pair_histogram.argtypes = [pp, dp, dp, C.c_double, C.c_int32, u64p, u64p]
         L.orc_set_log.argtypes = [C.POINTER(Event), C.c_int64]
         L.orc_log_count.restype = C.c_int64
         _lib = L
@@ -201,6 +202,19 @@ def psi6_box(n, L, x, y, r_cut=1.4):
 def psi6(p, x, y, r_cut=1.4):
     """psi6_box in the box of the parameters p."""
     return psi6_box(p.n, box_length(p.n, p.sigma, p.eta), x, y, r_cut)
+
+
+def pair_histogram(p, x, y, r_max, n_bins):
+    """Ordered-pair counts in bins [sigma + i delta, sigma + (i+1) delta),
+    delta = (r_max - sigma)/n_bins, and the number of pairs closer than sigma."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    counts = np.zeros(int(n_bins), dtype=np.uint64)
+    ov = C.c_uint64(0)
+    dp = C.POINTER(C.c_double)
+    lib().orc_pair_histogram(C.byref(p), x.ctypes.data_as(dp), y.ctypes.data_as(dp), float(r_max),
+                             int(n_bins), counts.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(ov))
+    return counts, ov.value
 
 
 def run_logged(p, x, y, sweep0, n_sweeps, capacity=1 << 20):

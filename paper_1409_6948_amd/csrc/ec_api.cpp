@@ -21,7 +21,7 @@ constexpr double kPi = 3.14159265358979323846;
 struct Layout {
   size_t dev, sweep_ctr, x, y, cell_of, cell_ids, cell_count, cell_fill, cell_start, acc_delta, acc_cnt,
       ring, cell_digest, draws, err, red, chain_start, chain_dir, shuffle, dbg, psi, psi_part, psi_red,
-      total;
+      gr, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -55,6 +55,7 @@ Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell) {
   l.psi = o;        o = align256(o + 16 * (size_t)n);
   l.psi_part = o;   o = align256(o + 24 * (((size_t)n + 255) / 256));
   l.psi_red = o;    o = align256(o + 32);
+  l.gr = o;         o = align256(o + 8 * (size_t)(ec::kMaxGrBins + 1));
   l.total = o;
   return l;
 }
@@ -149,6 +150,10 @@ struct ec_system_s {
   ec::PhaseEvents ev;
   double phase_ms;
   int64_t phase_launches;
+  // pair histogram series (pressure route)
+  double gr_rmax;
+  int32_t gr_bins;
+  int64_t gr_samples;
 };
 
 namespace {
@@ -264,6 +269,9 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   s->timing = false;
   s->phase_ms = 0.0;
   s->phase_launches = 0;
+  s->gr_rmax = 0.0;
+  s->gr_bins = 0;
+  s->gr_samples = 0;
   ec::Dev& d = s->dev;
   std::memset(&d, 0, sizeof d);
   d.x = (double*)(b + lay.x);
@@ -288,6 +296,7 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   d.psi = (double2*)(b + lay.psi);
   d.psi_part = (double*)(b + lay.psi_part);
   d.psi_red = (double*)(b + lay.psi_red);
+  d.gr_counts = (unsigned long long*)(b + lay.gr);
   d.search = (p->flags & EC_FLAG_SCAN_SEARCH) ? 1 : 0;
   d.n = p->n_disks;
   d.sigma = p->sigma;
@@ -328,6 +337,7 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   if (e == hipSuccess) e = hipMemsetAsync(d.dbg, 0, 8 * ec::kDebugWords, stream);
   if (e == hipSuccess) e = hipMemsetAsync(d.digest_ring, 0, 8 * ec::kDigestRing, stream);
   if (e == hipSuccess) e = hipMemsetAsync(d.cell_digest, 0, 8 * (size_t)d.C * (size_t)d.C, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.gr_counts, 0, 8 * (size_t)(ec::kMaxGrBins + 1), stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);  // the host record is copied by now
   if (e != hipSuccess) {
     ec_status r = hip_fail(s, e, "init");
@@ -461,6 +471,86 @@ ec_status ec_measure_psi6(ec_system s, double r_cut, double* psi_re, double* psi
   if (psi_re) *psi_re = red[0];
   if (psi_im) *psi_im = red[1];
   if (mean_neighbours) *mean_neighbours = red[2];
+  return EC_OK;
+}
+
+ec_status ec_gr_reset(ec_system s) {
+  if (!s) return EC_E_INVALID;
+  EC_HIP(s, hipMemsetAsync(s->dev.gr_counts, 0, 8 * (size_t)(ec::kMaxGrBins + 1), s->stream));
+  s->gr_samples = 0;
+  s->gr_bins = 0;
+  s->gr_rmax = 0.0;
+  return EC_OK;
+}
+
+ec_status ec_gr_accumulate(ec_system s, double r_max, int32_t n_bins) {
+  if (!s) return EC_E_INVALID;
+  const double limit = s->p.cells_per_side == 1 ? 0.5 * s->dv.L : s->dv.w;
+  if (!(r_max > s->p.sigma) || !(r_max <= limit) || n_bins < 1 || n_bins > ec::kMaxGrBins) {
+    s->last_error = "need sigma < r_max <= cell side (half the box for one cell), 1 <= n_bins <= 1024";
+    return EC_E_INVALID;
+  }
+  if (s->gr_samples == 0 || r_max != s->gr_rmax || n_bins != s->gr_bins) {
+    ec_status st = ec_gr_reset(s);  // a new series starts from zero counts
+    if (st != EC_OK) return st;
+  }
+  s->gr_rmax = r_max;
+  s->gr_bins = n_bins;
+  const double delta = (r_max - s->p.sigma) / (double)n_bins;
+  EC_HIP(s, ec::launch_gr(s->dev_d, s->shape, r_max, delta, n_bins, s->stream));
+  s->gr_samples += 1;
+  return EC_OK;
+}
+
+ec_status ec_gr_counts(ec_system s, uint64_t* counts, int64_t* samples, uint64_t* overlaps) {
+  if (!s || !counts) return EC_E_INVALID;
+  std::vector<uint64_t> h((size_t)ec::kMaxGrBins + 1);
+  EC_HIP(s, hipMemcpyAsync(h.data(), s->dev.gr_counts, 8 * h.size(), hipMemcpyDeviceToHost, s->stream));
+  ec_status st = check_err(s);
+  if (st != EC_OK) return st;
+  for (int32_t i = 0; i < s->gr_bins; ++i) counts[i] = h[(size_t)i];
+  if (samples) *samples = s->gr_samples;
+  if (overlaps) *overlaps = h[(size_t)s->gr_bins];
+  return EC_OK;
+}
+
+ec_status ec_gr_normalize(int64_t n_disks, double box, double sigma, double r_max, int32_t n_bins,
+                          const uint64_t* counts, int64_t samples, double fit_width, double* g,
+                          double* R, double* g_contact, double* z) {
+  if (n_disks < 2 || !(box > 0.0) || !(sigma > 0.0) || !(r_max > sigma) || n_bins < 1 || !counts ||
+      samples < 1 || !(fit_width > 0.0))
+    return EC_E_INVALID;
+  const double rho = (double)n_disks / (box * box);
+  const double delta = (r_max - sigma) / (double)n_bins;
+  // least-squares quadratic in x = R - sigma over the bins with x < fit_width
+  double sx[5] = {0, 0, 0, 0, 0}, sy[3] = {0, 0, 0};
+  int used = 0;
+  for (int32_t i = 0; i < n_bins; ++i) {
+    const double e0 = sigma + delta * i, e1 = sigma + delta * (i + 1);
+    const double area = kPi * (e1 * e1 - e0 * e0);
+    const double gi = (double)counts[i] / ((double)samples * (double)n_disks * rho * area);
+    const double Ri = 2.0 * (e1 * e1 * e1 - e0 * e0 * e0) / (3.0 * (e1 * e1 - e0 * e0));
+    if (g) g[i] = gi;
+    if (R) R[i] = Ri;
+    const double x = Ri - sigma;
+    if (x < fit_width) {
+      double p = 1.0;
+      for (int k = 0; k < 5; ++k) { sx[k] += p; if (k < 3) sy[k] += p * gi; p *= x; }
+      ++used;
+    }
+  }
+  if (used < 3) return EC_E_INVALID;
+  // normal equations [sx0 sx1 sx2; sx1 sx2 sx3; sx2 sx3 sx4] c = sy, Cramer's rule for c0
+  const double a00 = sx[0], a01 = sx[1], a02 = sx[2], a11 = sx[2], a12 = sx[3], a22 = sx[4];
+  const double det = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) +
+                     a02 * (a01 * a12 - a11 * a02);
+  if (!(std::fabs(det) > 0.0)) return EC_E_INVALID;
+  const double det0 = sy[0] * (a11 * a22 - a12 * a12) - a01 * (sy[1] * a22 - a12 * sy[2]) +
+                      a02 * (sy[1] * a12 - a11 * sy[2]);
+  const double gc = det0 / det;
+  if (g_contact) *g_contact = gc;
+  // eq. (pressure): beta P / rho = 1 + (pi/2) sigma^2 rho g(sigma+)
+  if (z) *z = 1.0 + 0.5 * kPi * sigma * sigma * rho * gc;
   return EC_OK;
 }
 

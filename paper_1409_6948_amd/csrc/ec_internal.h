@@ -38,6 +38,8 @@ constexpr int kMaxDrawTries = 256;
 constexpr int kDebugWords = 16;
 
 constexpr int kDigestRing = 1024;
+// Bins of the pair histogram (pressure route).
+constexpr int kMaxGrBins = 1024;
 // Events hashed together, one per lane, by the walled-cell kernel's digest
 // (event ids then fit in 29 bits: N < 2^29 - 3).
 constexpr int kDigestBatch = 64;
@@ -67,6 +69,7 @@ struct Dev {
   double2* psi;                     // [N] per-disk hexatic order Psi_k (re, im)
   double* psi_part;                 // [3 * ceil(N/256)] per-block sums (re, im, neighbours)
   double* psi_red;                  // [3] Psi (re, im) and the mean neighbour count
+  unsigned long long* gr_counts;    // [kMaxGrBins + 1] pair counts per bin, then pairs < sigma
 
   int64_t n;
   double sigma, sig2, ell, L, half_L, w, cap, b, inv_b, margin;
@@ -144,5 +147,9 @@ hipError_t launch_zero_tallies(const Dev* ds, int32_t n_cells, hipStream_t st);
 // r_cut <= cell side): rebin of the current sweep, per-disk Psi_k, and a
 // fixed-order reduction into psi_red.
 hipError_t launch_psi6(const Dev* ds, const LaunchShape& sh, double r_cut, hipStream_t st);
+// Add the current configuration's ordered-pair counts (bins of width delta =
+// (r_max - sigma)/n_bins from sigma; r_max <= cell side) to gr_counts.
+hipError_t launch_gr(const Dev* ds, const LaunchShape& sh, double r_max, double delta, int n_bins,
+                     hipStream_t st);
 
 }  // namespace ec

@@ -1267,6 +1267,57 @@ __global__ void __launch_bounds__(1024) k_psi6_final(const Dev* __restrict__ ds,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pair histogram for the pressure route of eq. (pressure), Sec. 2: one thread
+// per disk scans the 3 x 3 cells around its own (r_max <= cell side), minimum
+// image, bin = floor((sqrt(dx*dx + dy*dy) - sigma) / delta).  Counts go to a
+// per-block LDS histogram, then to the global one (integers: exact and
+// independent of order).  Pairs closer than sigma are counted apart.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_gr(const Dev* __restrict__ ds, double r_max, double delta,
+                                            int n_bins) {
+  const Dev d = ds[blockIdx.y];
+  __shared__ unsigned int hist[kMaxGrBins + 1];
+  for (int i = threadIdx.x; i <= n_bins; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < d.n) {
+    const double xk = d.x[k], yk = d.y[k];
+    const double L = d.L, half_L = d.half_L, r2max = r_max * r_max, sigma = d.sigma;
+    const int C = d.C;
+    const bool one_cell = C == 1;
+    const int c = one_cell ? 0 : d.cell_of[k];
+    const int cx = c % C, cy = c / C;
+    const int span = one_cell ? 0 : 1;
+    for (int oy = -span; oy <= span; ++oy) {
+      for (int ox = -span; ox <= span; ++ox) {
+        const int nc = ((cy + oy + C) % C) * C + (cx + ox + C) % C;
+        const int i0 = one_cell ? 0 : d.cell_start[nc];
+        const int i1 = one_cell ? (int)d.n : d.cell_start[nc + 1];
+        for (int i = i0; i < i1; ++i) {
+          const int l = one_cell ? i : d.cell_ids[i];
+          if (l == k) continue;
+          double dx = d.x[l] - xk, dy = d.y[l] - yk;
+          if (dx < -half_L) dx += L; else if (dx >= half_L) dx -= L;
+          if (dy < -half_L) dy += L; else if (dy >= half_L) dy -= L;
+          const double d2 = dx * dx + dy * dy;
+          if (!(d2 < r2max)) continue;
+          const double dist = sqrt(d2);
+          if (dist < sigma) {
+            atomicAdd(&hist[n_bins], 1u);
+            continue;
+          }
+          const double t = floor((dist - sigma) / delta);
+          if (t < (double)n_bins) atomicAdd(&hist[(int)t], 1u);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= n_bins; i += blockDim.x)
+    if (hist[i]) atomicAdd(&d.gr_counts[i], (unsigned long long)hist[i]);
+}
+
 // The sweep counter every kernel of the next sweep reads (one thread per system).
 __global__ void k_sweep_done(const Dev* __restrict__ ds) {
   if (threadIdx.x == 0) *ds[blockIdx.y].sweep_ctr += 1;
@@ -1352,6 +1403,20 @@ hipError_t launch_psi6(const Dev* ds, const LaunchShape& sh, double r_cut, hipSt
   }
   hipLaunchKernelGGL(k_psi6, dim3(nblk, 1), dim3(256), 0, st, ds, r_cut * r_cut);
   hipLaunchKernelGGL(k_psi6_final, dim3(1, 1), dim3(1024), 0, st, ds, (int)nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_gr(const Dev* ds, const LaunchShape& sh, double r_max, double delta, int n_bins,
+                     hipStream_t st) {
+  const unsigned nblk = (unsigned)((sh.max_n + 255) / 256);
+  if (!sh.periodic) {
+    // cell lists of the current sweep's grid (the next sweep builds the same ones)
+    hipLaunchKernelGGL(k_prep, dim3(1, 1), dim3(1024), 0, st, ds);
+    hipLaunchKernelGGL(k_count, dim3(nblk, 1), dim3(256), 0, st, ds);
+    hipLaunchKernelGGL(k_scan, dim3(1, 1), dim3(1024), 0, st, ds);
+    hipLaunchKernelGGL(k_scatter, dim3(nblk, 1), dim3(256), 0, st, ds);
+  }
+  hipLaunchKernelGGL(k_gr, dim3(nblk, 1), dim3(256), 0, st, ds, r_max, delta, n_bins);
   return hipGetLastError();
 }
 

@@ -27,7 +27,8 @@ EXPORTED = ("ec_workspace_bytes", "ec_init_system", "ec_sweep", "ec_measure_pres
             "ec_set_timing", "ec_get_timing", "ec_destroy", "ec_status_string",
             "ec_last_error", "ec_batch_workspace_bytes", "ec_init_batch", "ec_sweep_batch",
             "ec_batch_system", "ec_batch_set_graph", "ec_batch_set_cells_per_block",
-            "ec_batch_autotune", "ec_batch_last_error", "ec_destroy_batch", "ec_measure_psi6")
+            "ec_batch_autotune", "ec_batch_last_error", "ec_destroy_batch", "ec_measure_psi6",
+            "ec_gr_accumulate", "ec_gr_counts", "ec_gr_reset", "ec_gr_normalize")
 
 
 class ECError(RuntimeError):
@@ -69,6 +70,11 @@ def load_library():
         "ec_sweep": [vp, C.c_int64],
         "ec_measure_pressure": [vp, dp, dp, u64p],
         "ec_measure_psi6": [vp, C.c_double, dp, dp, dp, dp],
+        "ec_gr_accumulate": [vp, C.c_double, C.c_int32],
+        "ec_gr_counts": [vp, u64p, C.POINTER(C.c_int64), u64p],
+        "ec_gr_reset": [vp],
+        "ec_gr_normalize": [C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int32, u64p,
+                            C.c_int64, C.c_double, dp, dp, dp, dp],
         "ec_reset_tallies": [vp],
         "ec_get_positions": [vp, dp, dp, C.c_int64],
         "ec_set_positions": [vp, dp, dp, C.c_int64],
@@ -177,6 +183,24 @@ class System:
                self.h, "ec_measure_psi6")
         out = (complex(re.value, im.value), nb.value)
         return out + (per[0::2] + 1j * per[1::2],) if per_disk else out
+
+    def gr_accumulate(self, r_max, n_bins):
+        """Add the current configuration's ordered-pair counts to the histogram."""
+        self._gr = (float(r_max), int(n_bins))
+        _check(self._lib.ec_gr_accumulate(self.h, float(r_max), int(n_bins)), self.h,
+               "ec_gr_accumulate")
+
+    def gr_counts(self):
+        """(counts[n_bins], configurations added, pairs closer than sigma)."""
+        n_bins = self._gr[1]
+        counts = np.zeros(n_bins, dtype=np.uint64)
+        samples, ov = C.c_int64(), C.c_uint64()
+        _check(self._lib.ec_gr_counts(self.h, counts.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                      C.byref(samples), C.byref(ov)), self.h, "ec_gr_counts")
+        return counts, samples.value, ov.value
+
+    def gr_reset(self):
+        _check(self._lib.ec_gr_reset(self.h), self.h, "ec_gr_reset")
 
     def reset_tallies(self):
         _check(self._lib.ec_reset_tallies(self.h), self.h, "ec_reset_tallies")
@@ -304,3 +328,18 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def gr_normalize(n_disks, box, sigma, r_max, counts, samples, fit_width=0.05):
+    """Host-only normalisation of pair counts (ec_gr_normalize): returns
+    (g[n_bins], R[n_bins], g at contact, z = beta P / rho)."""
+    counts = np.ascontiguousarray(counts, dtype=np.uint64)
+    n = len(counts)
+    g = np.zeros(n)
+    R = np.zeros(n)
+    gc, z = C.c_double(), C.c_double()
+    _check(load_library().ec_gr_normalize(int(n_disks), float(box), float(sigma), float(r_max), n,
+                                          counts.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                          int(samples), float(fit_width), _dptr(g), _dptr(R),
+                                          C.byref(gc), C.byref(z)), what="ec_gr_normalize")
+    return g, R, gc.value, z.value

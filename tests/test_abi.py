@@ -108,3 +108,32 @@ def test_batch_init_rejects_small_workspace_without_touching_gpu():
     h = C.c_void_p()
     st = lib.ec_init_batch(ps, 2, C.c_void_p(0x1000), 16, None, C.byref(h))
     assert st == E.EC_E_NOMEM and not h.value
+
+
+def test_gr_normalize_recovers_a_quadratic_contact_value():
+    """Host-only normalisation (no GPU): counts built from a known g(R) near
+    contact give back g at contact and z = 1 + (pi/2) sigma^2 rho g(sigma+)."""
+    import math
+    import numpy as np
+    N, L, s, rmax, nb, samples = 4096, 80.0, 1.0, 1.5, 100, 10 ** 9
+    rho = N / L ** 2
+    e = s + (rmax - s) / nb * np.arange(nb + 1)
+    R = 2 * (e[1:] ** 3 - e[:-1] ** 3) / (3 * (e[1:] ** 2 - e[:-1] ** 2))
+    gtrue = 5.0 - 30.0 * (R - s) + 120.0 * (R - s) ** 2
+    counts = np.round(gtrue * samples * N * rho * math.pi * (e[1:] ** 2 - e[:-1] ** 2))
+    g, RR, gc, z = P.gr_normalize(N, L, s, rmax, counts.astype(np.uint64), samples, 0.05)
+    np.testing.assert_allclose(RR, R, rtol=1e-12)  # e^3 differences cancel: ~1e-14
+    np.testing.assert_allclose(g, gtrue, rtol=1e-9)
+    assert abs(gc - 5.0) < 1e-8
+    assert abs(z - (1 + math.pi / 2 * rho * gc)) < 1e-12
+
+
+def test_gr_normalize_rejects_bad_arguments():
+    import numpy as np
+    c = np.ones(10, dtype=np.uint64)
+    with pytest.raises(E.ECError):
+        P.gr_normalize(4096, 80.0, 1.0, 0.9, c, 1)       # r_max <= sigma
+    with pytest.raises(E.ECError):
+        P.gr_normalize(4096, 80.0, 1.0, 1.5, c, 0)       # no samples
+    with pytest.raises(E.ECError):
+        P.gr_normalize(4096, 80.0, 1.0, 1.5, c, 1, 0.01)  # fewer than 3 bins in the fit

@@ -533,3 +533,33 @@ def test_psi6_pair_isolated_disk_and_periodic_image():
     y2 = np.array([7.0, 7.0])
     _, nb2, per2 = O.psi6_box(2, L, x2, y2, 1.4)
     assert nb2 == 1.0 and abs(per2[0] - 1.0) < 1e-14 and abs(per2[1] - 1.0) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Pair histogram of the pressure route (eq. pressure)
+# ---------------------------------------------------------------------------
+def test_pair_histogram_start_lattice():
+    """Start lattice: every disk has 2 neighbours at distance a and 4 at
+    a sqrt(5)/2 inside 1.5 sigma, so the ordered-pair counts are 2N and 4N in
+    the bins holding those distances and 0 elsewhere."""
+    p = O.params(4096, 0.72, 20.0, 8)
+    x, y = O.lattice(p)
+    a = O.box_length(4096, 1.0, 0.72) / 64
+    counts, ov = O.pair_histogram(p, x, y, 1.5, 100)
+    d = 0.5 / 100
+    want = np.zeros(100, dtype=np.uint64)
+    want[int((a - 1.0) // d)] += 2 * 4096
+    want[int((a * math.sqrt(1.25) - 1.0) // d)] += 4 * 4096
+    np.testing.assert_array_equal(counts, want)
+    assert ov == 0
+
+
+def test_pair_histogram_single_pair_and_overlap():
+    p = O.params(4, 0.01, 20.0, 1)  # box of side ~17.7
+    L = O.box_length(4, 1.0, 0.01)
+    x = np.array([1.0, 2.2345, 9.0, 9.5])  # a pair at 1.2345: well inside bin 23
+    y = np.array([1.0, 1.0, 9.0, 9.0])
+    counts, ov = O.pair_histogram(p, x, y, 1.5, 50)
+    assert counts.sum() == 2 and counts[23] == 2
+    assert ov == 2  # the pair at distance 0.5, both orders
+    assert L > 10
