@@ -6,6 +6,13 @@ simulation cells, chain length 20 sigma, isotropic directions, FP64, starting
 from the lattice.  The metric is EC collisions (lifts) per second; sweeps per
 second and the whole-sweep fraction of HBM bandwidth are reported beside it.
 
+With --workload start-rules it runs the negative control of Sec. 3.4 (Fig. 2-3)
+instead: 8 systems with start disks drawn with replacement and 8 with a
+shuffled list of distinct disks (N = 16384, eta = 0.70, 16 x 16 cells, seeds
+1-8 each), batched, and reports the EC pressure of each rule (mean and
+standard error over the seeds) and their difference in units of the combined
+error.
+
 With --workload batch64 it times the batched form instead: the 64-system
 ensemble (N log-uniform in [4096, 262144], eta uniform in [0.30, 0.72], about
 64 disks per cell) advanced by shared launches, with the autotuned schedule
@@ -105,6 +112,8 @@ def main():
 
     if args.workload == "batch64":
         return bench_batch(args, torch, P)
+    if args.workload == "start-rules":
+        return bench_start_rules(args, torch, P)
     w = dict(inputs.WORKLOADS[args.workload])
     torch.cuda.set_device(0)
     prec = P.EC_PREC_FP64 if args.precision == "fp64" else P.EC_PREC_FP32_SCREEN
@@ -254,6 +263,57 @@ def bench_batch(args, torch, P):
     }
     print(json.dumps(line), flush=True)
 
+
+def bench_start_rules(args, torch, P):
+    """Negative control: pressure with starts drawn with replacement (the
+    correct rule, Fig. 2) against shuffled distinct starts (Fig. 3), n_m = n_c.
+    Both pressure routes are reported: the lift tallies (eq. EC pressure) and
+    g(r) extrapolated to contact (eq. pressure), the route of Fig. 3."""
+    import math
+    n, eta, C, ell, sigma = 16384, 0.70, 16, 20.0, 1.0
+    r_max, n_bins, fit = 1.5, 100, 0.05
+    box = math.sqrt(n * math.pi * sigma * sigma / (4.0 * eta))
+    ps = []
+    for rule in (P.EC_START_REPLACE, P.EC_START_DISTINCT):
+        for seed in range(1, 9):
+            ps.append(P.make_params(n, eta, ell, C, seed=seed, start_mode=rule, system=len(ps)))
+    b = P.Batch(ps)
+    b.set_graph(True)
+    b.sweep(args.warmup)
+    b.stream.synchronize()
+    for s in b.systems:
+        s.reset_tallies()
+        s.gr_reset()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.sweep(1)
+        for s in b.systems:
+            s.gr_accumulate(r_max, n_bins)
+    b.stream.synchronize()
+    secs = time.perf_counter() - t0
+    z_ec, z_gr = [], []
+    for s in b.systems:
+        z_ec.append(s.measure_pressure()[0])
+        counts, samples, _ = s.gr_counts()
+        z_gr.append(P.gr_normalize(n, box, sigma, r_max, counts, samples, fit)[3])
+
+    def stats(v):
+        m = sum(v) / len(v)
+        return m, math.sqrt(sum((x - m) ** 2 for x in v) / (len(v) - 1) / len(v))
+
+    out, diffs = {}, {}
+    for route, zs in (("ec", z_ec), ("gr_contact", z_gr)):
+        out[route] = {}
+        for name, part in (("replacement", zs[:8]), ("distinct", zs[8:])):
+            m, se = stats(part)
+            out[route][name] = {"z_mean": m, "z_stderr": se, "z_per_seed": part}
+        d = out[route]["distinct"]["z_mean"] - out[route]["replacement"]["z_mean"]
+        comb = math.hypot(out[route]["distinct"]["z_stderr"], out[route]["replacement"]["z_stderr"])
+        diffs[route] = {"z_difference": d, "in_combined_stderr": d / comb if comb > 0 else None}
+    line = {"workload": "start-rules", "n_disks": n, "eta": eta, "cells_per_side": C, "ell": ell,
+            "warmup": args.warmup, "sweeps": args.steps, "seconds": secs, "routes": out,
+            "distinct_minus_replacement": diffs}
+    print(json.dumps(line), flush=True)
 
 if __name__ == "__main__":
     main()

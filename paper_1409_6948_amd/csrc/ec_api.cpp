@@ -110,11 +110,17 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
     out->w = w;
     out->nb = nb;
     out->cap_own = own_capacity(w, p->sigma);
-    int32_t cpb = p->cells_per_block == 0 ? 1 : p->cells_per_block;
-    if (cpb != 1 && cpb != 2 && cpb != 4) { *why = "cells_per_block must be 0, 1, 2 or 4"; return EC_E_INVALID; }
-    out->cpb = cpb;
     out->lds_per_cell =
         ec::cell_lds_layout(nb + 2, out->cap_own, p->precision == EC_PREC_FP32_SCREEN).bytes;
+    // Default: four cells (four waves) per workgroup when their LDS fits one CU.
+    // The waves of one workgroup go to the four SIMDs of one CU; one-wave
+    // workgroups leave the SIMD choice to the dispatcher, which has been
+    // measured to put two waves on one SIMD for part of a launch (both then
+    // run about 25 % slower while another SIMD idles).
+    int32_t cpb = p->cells_per_block;
+    if (cpb == 0) cpb = (size_t)4 * out->lds_per_cell <= 160 * 1024 ? 4 : 1;
+    if (cpb != 1 && cpb != 2 && cpb != 4) { *why = "cells_per_block must be 0, 1, 2 or 4"; return EC_E_INVALID; }
+    out->cpb = cpb;
     if ((size_t)cpb * out->lds_per_cell > 160 * 1024) {
       *why = "LDS per workgroup exceeds 160 KiB"; return EC_E_UNSUPPORTED;
     }

@@ -118,8 +118,9 @@ def test_walled_cells(P, n, eta, cells, ell, sweeps):
     _compare_full(P, n, eta, ell, cells, 1, sweeps, seed=7)
 
 
-def test_walled_cells_four_per_workgroup(P):
-    _compare_full(P, 4096, 0.72, 20.0, 8, 1, 2, seed=8, cells_per_block=4)
+@pytest.mark.parametrize("cpb", [1, 2, 4])
+def test_walled_cells_per_workgroup(P, cpb):
+    _compare_full(P, 4096, 0.72, 20.0, 8, 1, 2, seed=8, cells_per_block=cpb)
 
 
 def test_fixed_chains_per_cell(P):
