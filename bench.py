@@ -47,13 +47,14 @@ FLOP_PER_EVENT = 100.0
 HBM_BYTES_PER_DISK = 16 + 8 + 8 + 20 + 16 + 20
 
 
-def measured_traffic(workload):
-    """HBM bytes per phase-kernel launch from the committed counter summary, or
-    None when the kernel source has changed since the counters were taken."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of the simulation-cell kernel from the committed
+    counter summary, or None when the kernel source has changed since the
+    counters were taken."""
     import hashlib
     import re
     src = os.path.join(ROOT, "paper_1409_6948_amd", "csrc", "ec_kernels.hip")
-    prof = os.path.join(ROOT, "profiles", f"k_phase_{workload}_counters.md")
+    prof = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
     if not os.path.exists(prof):
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -94,6 +95,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="pec_1m")
     ap.add_argument("--cells-per-block", type=int, default=0)
+    ap.add_argument("--schedule", choices=("one-launch", "phase-launches"), default="one-launch",
+                    help="all four colour phases of a sweep in one launch with per-cell "
+                         "dependencies (default), or one launch per phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "fp32-screen"), default="fp64",
                     help="fp32-screen: FP32 screening of candidates, FP64 for the survivors "
@@ -117,8 +121,11 @@ def main():
     w = dict(inputs.WORKLOADS[args.workload])
     torch.cuda.set_device(0)
     prec = P.EC_PREC_FP64 if args.precision == "fp64" else P.EC_PREC_FP32_SCREEN
+    flags = P.EC_FLAG_PHASE_LAUNCHES if args.schedule == "phase-launches" else 0
+    kernel = "k_phase" if args.schedule == "phase-launches" else "k_sweep_cells"
     p = P.make_params(w["n"], w["eta"], w["ell"], w["cells"], dir_mode=w["dir_mode"],
-                      seed=w["seed"], cells_per_block=args.cells_per_block, precision=prec)
+                      seed=w["seed"], cells_per_block=args.cells_per_block, precision=prec,
+                      flags=flags)
     g = P.System(p, device="cuda:0")
     if args.copy_probe_mb > 0:
         nbytes = args.copy_probe_mb << 20
@@ -173,19 +180,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_disks": w["n"], "eta": w["eta"],
                    "cells_per_side": w["cells"], "ell": w["ell"], "directions": "isotropic",
-                   "precision": args.precision, "start": "lattice", "sweeps_before_timing": args.warmup},
+                   "precision": args.precision, "schedule": args.schedule, "start": "lattice",
+                   "sweeps_before_timing": args.warmup},
         "sweeps_per_s": sweeps_s,
         "events_per_s": events / secs,
         "counts": counts,
         "z_timed_sweeps": z,
         "hbm_frac_whole_sweep": hbm_frac,
         "wall_s": wall,
-        "roofline": {"bound": "alu", "kernel": "k_phase", "achieved": achieved_tf,
+        "roofline": {"bound": "alu", "kernel": kernel, "achieved": achieved_tf,
                      "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VECTOR_PEAK_TF,
-                     "traffic": measured_traffic(args.workload),
+                     "traffic": measured_traffic(kernel, args.workload),
                      "avg_launch_ms": avg_phase_s * 1e3, "launches": launches,
-                     "phase_share_of_sweep": phase_ms / gpu_ms},
+                     "kernel_share_of_sweep": phase_ms / gpu_ms},
     }
     if not args.no_cpu_baseline:
         print("# CPU oracle baseline", file=sys.stderr, flush=True)

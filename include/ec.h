@@ -78,6 +78,12 @@ typedef enum {
 /* ec_params.flags */
 #define EC_FLAG_SCAN_SEARCH 1u  /* walled cells: search every staged disk for each event
                                    instead of the 4x4-bin window (same events, slower)     */
+#define EC_FLAG_PHASE_LAUNCHES 2u /* walled cells: one kernel launch per colour phase, the
+                                   launch boundary separating the phases (Sec. 3.4 as
+                                   written).  Default: all four phases in one launch, each
+                                   cell starting once its neighbours of earlier phases are
+                                   done; the results are identical (same positions, digests
+                                   and tallies), only the schedule differs.                */
 
 typedef struct {
   uint32_t abi_version;     /* must equal EC_ABI_VERSION                                    */
@@ -201,12 +207,23 @@ ec_status ec_get_cell_digests(ec_system sys, uint64_t* out);
 ec_status ec_get_sweep_count(ec_system sys, int64_t* sweeps);
 
 /* Timing of the simulation-cell kernels: with on != 0, every later ec_sweep
- * records HIP events around each colour-phase launch on the system's stream,
- * synchronises after each sweep and adds the phase durations up.  Switching
- * on or off clears the totals.  Off by default (sweeps stay asynchronous). */
+ * records HIP events around each launch of the simulation-cell kernel on the
+ * system's stream (one per sweep by default, four with EC_FLAG_PHASE_LAUNCHES,
+ * one for the periodic cell), synchronises after each sweep and adds the
+ * durations up.  Switching on or off clears the totals.  Off by default
+ * (sweeps stay asynchronous). */
 ec_status ec_set_timing(ec_system sys, int32_t on);
-/* Summed phase-kernel milliseconds and number of phase launches timed. */
+/* Summed simulation-cell kernel milliseconds and number of launches timed. */
 ec_status ec_get_timing(ec_system sys, double* phase_ms, int64_t* launches);
+
+/* One-launch sweep (walled cells, default schedule): upper limit of one
+ * cell's wait for its neighbours of earlier phases, in seconds (default 60).
+ * A wait that reaches it sets device error bit 16 and ends the sweep; the
+ * next synchronising call reports EC_E_STATE and the system must be
+ * initialised again.  0 fails every wait: a test of that error path.  Takes
+ * effect from the next sweep.  EC_E_INVALID for a negative or non-finite
+ * value; EC_E_STATE for a system of a batch. */
+ec_status ec_set_dep_wait_limit(ec_system sys, double seconds);
 
 /* Destroy the handle (does not free the caller's workspace).  Synchronises. */
 ec_status ec_destroy(ec_system sys);

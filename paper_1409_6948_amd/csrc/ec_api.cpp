@@ -21,10 +21,14 @@ constexpr double kPi = 3.14159265358979323846;
 struct Layout {
   size_t dev, sweep_ctr, x, y, cell_of, cell_ids, cell_count, cell_fill, cell_start, acc_delta, acc_cnt,
       ring, cell_digest, draws, err, red, chain_start, chain_dir, shuffle, dbg, psi, psi_part, psi_red,
-      gr, total;
+      gr, queue, cell_done, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// One-launch sweep: default limit of one dependency wait, 60 s of the 100 MHz
+// device clock.
+constexpr int64_t kDefaultDepWaitTicks = int64_t(60) * 100000000;
 
 Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell) {
   Layout l;
@@ -56,6 +60,8 @@ Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell) {
   l.psi_part = o;   o = align256(o + 24 * (((size_t)n + 255) / 256));
   l.psi_red = o;    o = align256(o + 32);
   l.gr = o;         o = align256(o + 8 * (size_t)(ec::kMaxGrBins + 1));
+  l.queue = o;      o = align256(o + 8);
+  l.cell_done = o;  o = align256(o + 8 * nc);
   l.total = o;
   return l;
 }
@@ -232,7 +238,7 @@ ec::LaunchShape shape_of(const ec::Dev& d, const ec_params& p) {
   sh.max_active = (d.C / 2) * (d.C / 2);
   sh.cpb = d.cells_per_block;
   sh.max_lds_per_cell = d.lds_per_cell;
-  (void)p;
+  sh.one_launch = d.C > 1 && !(p.flags & EC_FLAG_PHASE_LAUNCHES);
   return sh;
 }
 
@@ -303,6 +309,9 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   d.psi_part = (double*)(b + lay.psi_part);
   d.psi_red = (double*)(b + lay.psi_red);
   d.gr_counts = (unsigned long long*)(b + lay.gr);
+  d.queue = (int32_t*)(b + lay.queue);
+  d.cell_done = (int64_t*)(b + lay.cell_done);
+  d.dep_wait_ticks = kDefaultDepWaitTicks;
   d.search = (p->flags & EC_FLAG_SCAN_SEARCH) ? 1 : 0;
   d.n = p->n_disks;
   d.sigma = p->sigma;
@@ -343,6 +352,8 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   if (e == hipSuccess) e = hipMemsetAsync(d.dbg, 0, 8 * ec::kDebugWords, stream);
   if (e == hipSuccess) e = hipMemsetAsync(d.digest_ring, 0, 8 * ec::kDigestRing, stream);
   if (e == hipSuccess) e = hipMemsetAsync(d.cell_digest, 0, 8 * (size_t)d.C * (size_t)d.C, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.cell_done, 0, 8 * (size_t)d.C * (size_t)d.C, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.queue, 0, 8, stream);
   if (e == hipSuccess) e = hipMemsetAsync(d.gr_counts, 0, 8 * (size_t)(ec::kMaxGrBins + 1), stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);  // the host record is copied by now
   if (e != hipSuccess) {
@@ -375,7 +386,7 @@ ec_status ec_sweep(ec_system s, int64_t n_sweeps) {
     if (s->timing) {
       EC_HIP(s, ec::launch_sweep(s->dev_d, s->shape, s->stream, &s->ev));
       EC_HIP(s, hipStreamSynchronize(s->stream));
-      int nq = s->p.cells_per_side == 1 ? 1 : 4;
+      int nq = (s->shape.periodic || s->shape.one_launch) ? 1 : 4;
       for (int q = 0; q < nq; ++q) {
         float ms = 0.f;
         EC_HIP(s, hipEventElapsedTime(&ms, s->ev.begin[q], s->ev.end[q]));
@@ -419,6 +430,16 @@ ec_status ec_get_timing(ec_system s, double* phase_ms, int64_t* launches) {
   return EC_OK;
 }
 
+ec_status ec_set_dep_wait_limit(ec_system s, double seconds) {
+  if (!s || !(seconds >= 0.0) || !std::isfinite(seconds)) return EC_E_INVALID;
+  if (s->in_batch) return EC_E_STATE;
+  const double ticks = seconds * 1e8;
+  s->dev.dep_wait_ticks = ticks >= 9.0e18 ? INT64_MAX : (int64_t)ticks;
+  EC_HIP(s, hipMemcpyAsync(s->dev_d, &s->dev, sizeof(ec::Dev), hipMemcpyHostToDevice, s->stream));
+  EC_HIP(s, hipStreamSynchronize(s->stream));  // the host record may change again at once
+  return EC_OK;
+}
+
 static ec_status check_err(ec_system s) {
   int32_t err[2] = {0, 0};
   double dbg[ec::kDebugWords];
@@ -429,7 +450,8 @@ static ec_status check_err(ec_system s) {
     char buf[512];
     std::snprintf(buf, sizeof buf,
                   "device check failed (bits 0x%x: 1 cell capacity, 2 bin capacity, 4 events per "
-                  "chain, 8 draw retries); first tripped chain: cell %.0f chain %.0f sweep %.0f "
+                  "chain, 8 draw retries, 16 dependency wait); first tripped chain: cell %.0f "
+                  "chain %.0f sweep %.0f "
                   "phase %.0f pos (%.17g, %.17g) dir (%.17g, %.17g) rem %.17g slot %.0f id %.0f "
                   "n_own %.0f",
                   err[0], dbg[0], dbg[1], dbg[2], dbg[3], dbg[4], dbg[5], dbg[6], dbg[7], dbg[8],
@@ -715,6 +737,9 @@ ec_status batch_layout(const ec_params* ps, int32_t n, BatchLayout* bl, std::vec
     if (ps[i].precision != ps[0].precision) {
       *why = "the systems of a batch share one precision"; return EC_E_UNSUPPORTED;
     }
+    if ((ps[i].flags ^ ps[0].flags) & EC_FLAG_PHASE_LAUNCHES) {
+      *why = "the systems of a batch share one schedule"; return EC_E_UNSUPPORTED;
+    }
     bl->off[(size_t)i] = o;
     o = align256(o + make_layout(ps[i].n_disks, ps[i].cells_per_side, ps[i].chains_per_cell).total);
   }
@@ -824,6 +849,7 @@ ec_status ec_init_batch(const ec_params* ps, int32_t n_sys, void* ws, size_t ws_
   sh.n_sys = n_sys;
   sh.periodic = false;
   sh.fp32_screen = ps[0].precision == EC_PREC_FP32_SCREEN;
+  sh.one_launch = !(ps[0].flags & EC_FLAG_PHASE_LAUNCHES);
   sh.cpb = 1;
   for (int32_t i = 0; i < n_sys; ++i) {
     ec_params p = ps[i];

@@ -21,7 +21,8 @@ enum {
   ERR_OWN_CAP = 1,     // a cell (own or neighbour) holds more disks than the packing bound
   ERR_BIN_CAP = 2,     // more than four centres in one LDS bin
   ERR_EVENT_CAP = 4,   // a chain exceeded kMaxEventsPerChain events
-  ERR_DRAW_CAP = 8     // a rejection draw exceeded kMaxDrawTries attempts
+  ERR_DRAW_CAP = 8,    // a rejection draw exceeded kMaxDrawTries attempts
+  ERR_DEP_WAIT = 16    // a cell waited longer than dep_wait_ticks for a neighbour of an earlier phase
 };
 
 // Events allowed in one chain before the sweep gives up with ERR_EVENT_CAP.
@@ -70,6 +71,8 @@ struct Dev {
   double* psi_part;                 // [3 * ceil(N/256)] per-block sums (re, im, neighbours)
   double* psi_red;                  // [3] Psi (re, im) and the mean neighbour count
   unsigned long long* gr_counts;    // [kMaxGrBins + 1] pair counts per bin, then pairs < sigma
+  int32_t* queue;                   // [1] ticket counter of the one-launch sweep
+  int64_t* cell_done;               // [C*C] last sweep + 1 whose write-back the cell has published
 
   int64_t n;
   double sigma, sig2, ell, L, half_L, w, cap, b, inv_b, margin;
@@ -80,6 +83,7 @@ struct Dev {
   int32_t C, nb, gridb, cap_own, chains_per_cell, dir_mode, start_mode, precision;
   int32_t lds_per_cell, cells_per_block;
   int32_t search;                   // 0: 4x4-bin window with guard; 1: scan of every slot
+  int64_t dep_wait_ticks;           // one-launch sweep: limit of one wait, 100 MHz clock ticks
   uint64_t seed;
   uint32_t system;
 };
@@ -120,6 +124,7 @@ struct LaunchShape {
   bool periodic;            // one periodic cell (single system only)
   bool any_distinct;        // some system uses the distinct-start control
   bool fp32_screen;         // the FP32-screened phase kernel (same for all)
+  bool one_launch;          // all four phases in one launch (k_sweep_cells), else one per phase
   int64_t max_n;            // disks
   int64_t max_chains;       // chains per sweep
   int32_t max_cells;        // C * C
@@ -128,7 +133,8 @@ struct LaunchShape {
   int32_t max_lds_per_cell; // bytes
 };
 
-// Optional HIP events recorded around every phase launch (begin[q], end[q]).
+// Optional HIP events recorded around every phase launch (begin[q], end[q]);
+// the one-launch sweep and the periodic cell use begin[0], end[0] only.
 struct PhaseEvents {
   hipEvent_t begin[4], end[4];
 };

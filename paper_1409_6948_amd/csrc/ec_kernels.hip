@@ -342,6 +342,7 @@ __global__ void k_prep(const Dev* __restrict__ ds) {
     decode_perm(draw_index(st, 24), dr.perm);
     *d.draws = dr;
     d.digest_ring[sweep % kDigestRing] = 0;
+    *d.queue = 0;  // ticket counter of the one-launch sweep
   }
 }
 
@@ -524,18 +525,15 @@ __device__ __forceinline__ int32_t load_err(const Dev& d) {
 }
 
 // PREC 0: FP64 contact distances; PREC 1: FP32 screen, FP64 for the survivors.
+// One active cell of colour phase q (Sec. 3.4, steps 3-6): stage the own
+// disks and the frozen band into LDS, run the cell's chains, write back.  One
+// wavefront; base is its LDS region.  Returns early, with d.err set, when a
+// capacity check fails.
 template <int PREC>
-__global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q) {
-  const Dev d = ds[blockIdx.y];
-  const int64_t sweep = *d.sweep_ctr;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+__device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, const SweepDraws& dr,
+                                           const int q, const int blk, unsigned char* const base,
+                                           const int lane) {
   const int half = d.C >> 1;
-  const int blk = blockIdx.x * d.cells_per_block + wave;
-  if (blk >= half * half) return;  // the whole wave leaves; no workgroup barrier follows
-
-  const SweepDraws dr = *d.draws;
   const int colour = dr.perm[q & 3];
   const int cx = 2 * (blk % half) + (colour & 1);
   const int cy = 2 * (blk / half) + (colour >> 1);
@@ -546,7 +544,6 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
   const int nslots = gridb * gridb * 4;
 
   const CellLds lay = cell_lds_layout(gridb, d.cap_own, PREC == 1);
-  unsigned char* base = lds_raw + (size_t)wave * d.lds_per_cell;
   double2* pos = (double2*)(base + lay.off_pos);
   uint64_t* meta = (uint64_t*)(base + lay.off_meta);
   int32_t* mask = (int32_t*)(base + lay.off_mask);
@@ -1019,6 +1016,108 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
   }
 }
 
+// Colour phase q of a sweep: one launch per phase, one wavefront per active
+// cell; the launch boundary separates the phases.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q) {
+  const Dev d = ds[blockIdx.y];
+  const int64_t sweep = *d.sweep_ctr;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int half = d.C >> 1;
+  const int blk = blockIdx.x * d.cells_per_block + wave;
+  if (blk >= half * half) return;  // the whole wave leaves; no workgroup barrier follows
+  const SweepDraws dr = *d.draws;
+  phase_cell<PREC>(d, sweep, dr, q, blk, lds_raw + (size_t)wave * d.lds_per_cell, lane);
+}
+
+// All four colour phases of a sweep in one launch.  The phases order only
+// neighbouring cells: a cell of phase q reads the disks of its eight
+// neighbours (frozen band) and writes its own, so it must follow the
+// neighbours of earlier phases and precede those of later ones, while cells
+// farther apart share nothing.  Each wavefront takes tickets from a counter
+// in phase order (ticket = q * C^2/4 + block), waits until the neighbours of
+// earlier phases have published this sweep's epoch, runs the cell and
+// publishes its own epoch.  Every cell then reads exactly the positions the
+// phase-by-phase schedule gives it, so the results are identical; a cell no
+// longer waits for the slowest cell of the previous phase anywhere in the
+// system.
+//
+// Progress: a wave waits only for cells with smaller tickets, which were
+// taken by waves already running, so by induction over tickets every wait
+// ends.  Every wait is also bounded by d.dep_wait_ticks (100 MHz clock) and
+// abandoned when any wave has set d.err: on either, the wave sets or sees the
+// error and leaves, and the sweep reports it.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_sweep_cells(const Dev* __restrict__ ds) {
+  const Dev d = ds[blockIdx.y];
+  const int64_t sweep = *d.sweep_ctr;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  unsigned char* const base = lds_raw + (size_t)wave * d.lds_per_cell;
+  const SweepDraws dr = *d.draws;
+  const int half = d.C >> 1;
+  const int per_phase = half * half;
+  const int64_t epoch = sweep + 1;
+  // phase of each colour, two bits per colour
+  int phase_of = 0;
+  for (int q = 0; q < 4; ++q) phase_of |= q << (2 * (dr.perm[q] & 3));
+
+  for (;;) {
+    int t = 0;
+    if (lane == 0) t = atomicAdd(d.queue, 1);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if (t >= 4 * per_phase) break;
+    const int q = t / per_phase;
+    const int blk = t - q * per_phase;
+    const int colour = dr.perm[q];
+    const int cx = 2 * (blk % half) + (colour & 1);
+    const int cy = 2 * (blk / half) + (colour >> 1);
+    if (q > 0) {
+      // lanes 0-7 watch the eight neighbours; those of earlier phases count
+      bool need = false;
+      int nc = 0;
+      if (lane < 8) {
+        const int k = lane < 4 ? lane : lane + 1;  // the 3 x 3 block without its centre
+        const int ncx = (cx + (k % 3) - 1 + d.C) % d.C;
+        const int ncy = (cy + (k / 3) - 1 + d.C) % d.C;
+        nc = ncy * d.C + ncx;
+        need = ((phase_of >> (2 * ((ncx & 1) | ((ncy & 1) << 1)))) & 3) < q;
+      }
+      const uint64_t t0 = wall_clock64();
+      bool ok = true;
+      for (;;) {
+        // the limit is tested first, so a limit of 0 fails every wait
+        if (wall_clock64() - t0 >= (uint64_t)d.dep_wait_ticks) {
+          if (lane == 0) atomicOr(d.err, ERR_DEP_WAIT);
+          ok = false;
+          break;
+        }
+        const bool ready =
+            !need || __hip_atomic_load(d.cell_done + nc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+        if (__builtin_amdgcn_ballot_w64(!ready) == 0) break;
+        if (__builtin_amdgcn_readfirstlane(load_err(d)) != 0) {
+          ok = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(4);
+      }
+      if (!ok) break;
+      // the neighbours' write-backs are visible to the staging loads below
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    phase_cell<PREC>(d, sweep, dr, q, blk, base, lane);
+    // this cell's write-back before its flag
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0)
+      __hip_atomic_store(d.cell_done + (cy * d.C + cx), epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__builtin_amdgcn_readfirstlane(load_err(d)) != 0) break;
+    wave_sync();  // LDS reads of this cell before the next cell's staging writes
+  }
+}
+
 // ---------------------------------------------------------------------------
 // One periodic cell (C = 1): all N disks in LDS, brute-force search with the
 // minimum image; flights longer than L/2 - sigma are split (free-flight cap).
@@ -1344,11 +1443,13 @@ hipError_t launch_zero_tallies(const Dev* ds, int32_t n_cells, hipStream_t st) {
 }
 
 hipError_t set_phase_lds_limit(int bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_phase<0>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_phase<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             bytes);
+  const void* fns[4] = {(const void*)k_phase<0>, (const void*)k_phase<1>, (const void*)k_sweep_cells<0>,
+                        (const void*)k_sweep_cells<1>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_reduce(const Dev* ds, hipStream_t st) {
@@ -1380,6 +1481,17 @@ hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
   const int cpb = sh.cpb;
   const unsigned grid = (unsigned)((sh.max_active + cpb - 1) / cpb);
   const size_t lds = (size_t)cpb * sh.max_lds_per_cell;
+  if (sh.one_launch) {
+    // as many wavefronts as one phase has cells; each takes cells of all phases
+    if (ev) (void)hipEventRecord(ev->begin[0], st);
+    if (sh.fp32_screen)
+      hipLaunchKernelGGL(k_sweep_cells<1>, dim3(grid, ns), dim3(64 * cpb), lds, st, ds);
+    else
+      hipLaunchKernelGGL(k_sweep_cells<0>, dim3(grid, ns), dim3(64 * cpb), lds, st, ds);
+    if (ev) (void)hipEventRecord(ev->end[0], st);
+    hipLaunchKernelGGL(k_sweep_done, dim3(1, ns), dim3(64), 0, st, ds);
+    return hipGetLastError();
+  }
   for (int q = 0; q < 4; ++q) {
     if (ev) (void)hipEventRecord(ev->begin[q], st);
     if (sh.fp32_screen)

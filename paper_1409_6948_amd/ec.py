@@ -17,6 +17,7 @@ EC_DIR_XY, EC_DIR_ISOTROPIC, EC_DIR_X = 0, 1, 2
 EC_PREC_FP64, EC_PREC_FP32_SCREEN = 0, 1
 EC_START_REPLACE, EC_START_DISTINCT = 0, 1
 EC_FLAG_SCAN_SEARCH = 1
+EC_FLAG_PHASE_LAUNCHES = 2
 EC_ABI_VERSION = 1
 COUNT_NAMES = ("lifts", "frozen", "walls", "chains", "pseudo")
 
@@ -24,7 +25,7 @@ COUNT_NAMES = ("lifts", "frozen", "walls", "chains", "pseudo")
 EXPORTED = ("ec_workspace_bytes", "ec_init_system", "ec_sweep", "ec_measure_pressure",
             "ec_reset_tallies", "ec_get_positions", "ec_set_positions", "ec_get_digests",
             "ec_get_cell_tallies", "ec_get_cell_digests", "ec_get_sweep_count",
-            "ec_set_timing", "ec_get_timing", "ec_destroy", "ec_status_string",
+            "ec_set_timing", "ec_get_timing", "ec_set_dep_wait_limit", "ec_destroy", "ec_status_string",
             "ec_last_error", "ec_batch_workspace_bytes", "ec_init_batch", "ec_sweep_batch",
             "ec_batch_system", "ec_batch_set_graph", "ec_batch_set_cells_per_block",
             "ec_batch_autotune", "ec_batch_last_error", "ec_destroy_batch", "ec_measure_psi6",
@@ -84,6 +85,7 @@ def load_library():
         "ec_get_sweep_count": [vp, C.POINTER(C.c_int64)],
         "ec_set_timing": [vp, C.c_int32],
         "ec_get_timing": [vp, dp, C.POINTER(C.c_int64)],
+        "ec_set_dep_wait_limit": [vp, C.c_double],
         "ec_destroy": [vp],
         "ec_batch_workspace_bytes": [P, C.c_int32, C.POINTER(C.c_size_t)],
         "ec_init_batch": [P, C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)],
@@ -239,6 +241,10 @@ class System:
         _check(self._lib.ec_get_cell_digests(self.h, out.ctypes.data_as(C.POINTER(C.c_uint64))),
                self.h, "ec_get_cell_digests")
         return out
+
+    def set_dep_wait_limit(self, seconds):
+        """Limit of one cell's wait for its earlier-phase neighbours (one-launch sweep)."""
+        _check(self._lib.ec_set_dep_wait_limit(self.h, float(seconds)), self.h, "ec_set_dep_wait_limit")
 
     def set_timing(self, on):
         _check(self._lib.ec_set_timing(self.h, 1 if on else 0), self.h, "ec_set_timing")

@@ -100,6 +100,10 @@ def test_batch_rejects_periodic_systems_and_empty_batches():
     lib = P.load_library()
     n = C.c_size_t()
     assert lib.ec_batch_workspace_bytes(C.byref(good), 0, C.byref(n)) == E.EC_E_INVALID
+    with pytest.raises(E.ECError) as ei:  # one schedule per batch
+        P.batch_workspace_bytes([good, P.make_params(65536, 0.70, 20.0, 16,
+                                                     flags=E.EC_FLAG_PHASE_LAUNCHES)])
+    assert ei.value.status == E.EC_E_UNSUPPORTED
 
 
 def test_batch_init_rejects_small_workspace_without_touching_gpu():

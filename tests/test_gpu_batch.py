@@ -95,6 +95,22 @@ def test_batch_graph_and_schedule_keep_trajectories(P, cpb):
     b.close()
 
 
+def test_batch_phase_launches_equal_one_launch_solo_runs(P):
+    cfgs = inputs.batch_systems(64, seed=0)[:12]
+    ps = _params(P, cfgs)
+    sweeps = 2
+    _say("[batch] phase-launch schedule against one-launch solo runs")
+    solos = _solo_states(P, ps, sweeps)
+    for p in ps:
+        p.flags |= P.EC_FLAG_PHASE_LAUNCHES
+    b = P.Batch(ps)
+    b.set_graph(True)
+    b.sweep(sweeps)
+    b.stream.synchronize()
+    _assert_same(b, solos, sweeps)
+    b.close()
+
+
 def test_autotune_leaves_the_state_untouched(P):
     cfgs = inputs.batch_systems(64, seed=0)[:12]
     ps = _params(P, cfgs)

@@ -123,6 +123,54 @@ def test_walled_cells_per_workgroup(P, cpb):
     _compare_full(P, 4096, 0.72, 20.0, 8, 1, 2, seed=8, cells_per_block=cpb)
 
 
+@pytest.mark.parametrize("n,eta,cells,ell,sweeps,cpb", [
+    (4096, 0.72, 8, 20.0, 3, 0),
+    (2304, 0.65, 6, 12.0, 3, 1),
+])
+def test_walled_cells_phase_launches(P, n, eta, cells, ell, sweeps, cpb):
+    """One launch per colour phase (the launch boundary as the barrier) gives
+    the same positions, digests and tallies as the default one-launch sweep."""
+    _compare_full(P, n, eta, ell, cells, 1, sweeps, seed=7, cells_per_block=cpb,
+                  flags=P.EC_FLAG_PHASE_LAUNCHES)
+
+
+def test_schedules_agree_at_full_size(P):
+    """N = 1,048,576, eta = 0.72, 64 x 64 cells, ell = 20 sigma, 3 sweeps: the
+    one-launch sweep of the bench equals the phase-by-phase sweep bit for bit."""
+    _say("[parity] pec_1m: one-launch vs phase launches, 3 sweeps")
+    out = []
+    for flags in (0, P.EC_FLAG_PHASE_LAUNCHES):
+        g = _gpu_system(P, 1048576, 0.72, 20.0, 64, 1, seed=1, flags=flags)
+        g.sweep(3)
+        out.append(g.get_positions() + (g.get_digests(3),) + g.get_cell_tallies())
+        g.close()
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_dependency_wait_limit(P):
+    """A wait limit of 0 fails every wait of the one-launch sweep: the sweep
+    ends with device error bit 16, reported by the next synchronising call.
+    The phase-launch schedule has no waits and ignores the limit."""
+    import paper_1409_6948_amd.ec as E
+    g = _gpu_system(P, 4096, 0.70, 10.0, 8, 1, seed=5)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(E.ECError) as ei:
+            g.set_dep_wait_limit(bad)
+        assert ei.value.status == E.EC_E_INVALID
+    g.set_dep_wait_limit(0.0)
+    _say("[parity] wait limit 0: expecting device error bit 16")
+    with pytest.raises(E.ECError) as ei:
+        g.sweep(1)
+        g.get_positions()
+    assert ei.value.status == E.EC_E_STATE
+    assert "bits 0x10" in str(ei.value)
+    h = _gpu_system(P, 4096, 0.70, 10.0, 8, 1, seed=5, flags=P.EC_FLAG_PHASE_LAUNCHES)
+    h.set_dep_wait_limit(0.0)
+    h.sweep(1)
+    h.get_positions()
+
+
 def test_fixed_chains_per_cell(P):
     _compare_full(P, 1024, 0.60, 5.0, 4, 1, 4, seed=9, chains_per_cell=7)
 
