@@ -47,6 +47,11 @@ FLOP_PER_EVENT = 100.0
 HBM_BYTES_PER_DISK = 16 + 8 + 8 + 20 + 16 + 20
 
 
+SCHEDULE_FLAGS = {"auto": lambda P: 0,
+                  "one-launch": lambda P: P.EC_FLAG_ONE_LAUNCH,
+                  "phase-launches": lambda P: P.EC_FLAG_PHASE_LAUNCHES}
+
+
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of the simulation-cell kernel from the committed
     counter summary, or None when the kernel source has changed since the
@@ -95,9 +100,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="pec_1m")
     ap.add_argument("--cells-per-block", type=int, default=0)
-    ap.add_argument("--schedule", choices=("one-launch", "phase-launches"), default="one-launch",
+    ap.add_argument("--schedule", choices=("auto", "one-launch", "phase-launches"), default="auto",
                     help="all four colour phases of a sweep in one launch with per-cell "
-                         "dependencies (default), or one launch per phase")
+                         "dependencies, or one launch per phase; auto = the library's default "
+                         "(one launch for a system alone, phase launches for a batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "fp32-screen"), default="fp64",
                     help="fp32-screen: FP32 screening of candidates, FP64 for the survivors "
@@ -121,7 +127,7 @@ def main():
     w = dict(inputs.WORKLOADS[args.workload])
     torch.cuda.set_device(0)
     prec = P.EC_PREC_FP64 if args.precision == "fp64" else P.EC_PREC_FP32_SCREEN
-    flags = P.EC_FLAG_PHASE_LAUNCHES if args.schedule == "phase-launches" else 0
+    flags = SCHEDULE_FLAGS[args.schedule](P)
     kernel = "k_phase" if args.schedule == "phase-launches" else "k_sweep_cells"
     p = P.make_params(w["n"], w["eta"], w["ell"], w["cells"], dir_mode=w["dir_mode"],
                       seed=w["seed"], cells_per_block=args.cells_per_block, precision=prec,
@@ -180,7 +186,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_disks": w["n"], "eta": w["eta"],
                    "cells_per_side": w["cells"], "ell": w["ell"], "directions": "isotropic",
-                   "precision": args.precision, "schedule": args.schedule, "start": "lattice",
+                   "precision": args.precision,
+                   "schedule": "phase-launches" if kernel == "k_phase" else "one-launch",
+                   "start": "lattice",
                    "sweeps_before_timing": args.warmup},
         "sweeps_per_s": sweeps_s,
         "events_per_s": events / secs,
@@ -207,8 +215,9 @@ def bench_batch(args, torch, P):
     """Aggregate lifts/s of the 64-system ensemble in the batched form, and the
     same sweeps run system by system (solo launches, one system after another)."""
     cfgs = inputs.batch_systems(64, seed=0)
+    flags = SCHEDULE_FLAGS[args.schedule](P)
     ps = [P.make_params(c["n"], c["eta"], c["ell"], c["cells"], dir_mode=c["dir_mode"],
-                        seed=c["seed"], system=i) for i, c in enumerate(cfgs)]
+                        seed=c["seed"], system=i, flags=flags) for i, c in enumerate(cfgs)]
     torch.cuda.set_device(0)
     b = P.Batch(ps)
     print(f"# batch64: {len(ps)} systems, sum N = {sum(c['n'] for c in cfgs)}", file=sys.stderr,
@@ -263,7 +272,9 @@ def bench_batch(args, torch, P):
         "data": "synthetic",
         "config": {"workload": "batch64", "n_systems": len(ps),
                    "sum_n": int(sum(c["n"] for c in cfgs)), "eta_range": [0.30, 0.72],
-                   "ell": 20.0, "cells_per_block": cpb, "hip_graph": True},
+                   "ell": 20.0, "cells_per_block": cpb,
+                   "schedule": "one-launch" if args.schedule == "one-launch" else "phase-launches",
+                   "hip_graph": True},
         "events_per_s": events / secs,
         "autotune_trial_ms": trials,
         "solo_sequential_s": solo_secs,

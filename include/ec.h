@@ -78,12 +78,18 @@ typedef enum {
 /* ec_params.flags */
 #define EC_FLAG_SCAN_SEARCH 1u  /* walled cells: search every staged disk for each event
                                    instead of the 4x4-bin window (same events, slower)     */
-#define EC_FLAG_PHASE_LAUNCHES 2u /* walled cells: one kernel launch per colour phase, the
-                                   launch boundary separating the phases (Sec. 3.4 as
-                                   written).  Default: all four phases in one launch, each
-                                   cell starting once its neighbours of earlier phases are
-                                   done; the results are identical (same positions, digests
-                                   and tallies), only the schedule differs.                */
+/* Schedule of the walled-cell sweep.  The results are identical either way
+ * (same positions, digests and tallies); only the timing differs.
+ *   one launch:    all four colour phases in one kernel launch, each cell
+ *                  starting once its neighbours of earlier phases are done;
+ *                  the default of a system swept alone.
+ *   phase launches: one launch per colour phase, the launch boundary
+ *                  separating the phases (Sec. 3.4 as written); the default
+ *                  of a batch, whose waiting cells would otherwise hold
+ *                  wavefront slots that other systems' cells can use.
+ * Setting both bits is EC_E_INVALID; the systems of a batch share them. */
+#define EC_FLAG_PHASE_LAUNCHES 2u
+#define EC_FLAG_ONE_LAUNCH 4u
 
 typedef struct {
   uint32_t abi_version;     /* must equal EC_ABI_VERSION                                    */

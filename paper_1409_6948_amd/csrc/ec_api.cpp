@@ -85,6 +85,9 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
   if (p->abi_version != EC_ABI_VERSION) { *why = "abi_version mismatch"; return EC_E_INVALID; }
   if (p->n_disks < 1 || p->n_disks > 0x7FFFFFF0LL) { *why = "n_disks out of range"; return EC_E_INVALID; }
   if (!(p->sigma > 0.0) || !std::isfinite(p->sigma)) { *why = "sigma must be > 0"; return EC_E_INVALID; }
+  if ((p->flags & EC_FLAG_PHASE_LAUNCHES) && (p->flags & EC_FLAG_ONE_LAUNCH)) {
+    *why = "EC_FLAG_PHASE_LAUNCHES and EC_FLAG_ONE_LAUNCH exclude each other"; return EC_E_INVALID;
+  }
   if (!(p->eta > 0.0) || !(p->eta < kPi / (2.0 * std::sqrt(3.0)))) {
     *why = "eta must lie in (0, pi/(2 sqrt 3))"; return EC_E_INVALID;
   }
@@ -238,7 +241,7 @@ ec::LaunchShape shape_of(const ec::Dev& d, const ec_params& p) {
   sh.max_active = (d.C / 2) * (d.C / 2);
   sh.cpb = d.cells_per_block;
   sh.max_lds_per_cell = d.lds_per_cell;
-  sh.one_launch = d.C > 1 && !(p.flags & EC_FLAG_PHASE_LAUNCHES);
+  sh.one_launch = d.C > 1 && !(p.flags & EC_FLAG_PHASE_LAUNCHES);  // a system swept alone
   return sh;
 }
 
@@ -737,7 +740,7 @@ ec_status batch_layout(const ec_params* ps, int32_t n, BatchLayout* bl, std::vec
     if (ps[i].precision != ps[0].precision) {
       *why = "the systems of a batch share one precision"; return EC_E_UNSUPPORTED;
     }
-    if ((ps[i].flags ^ ps[0].flags) & EC_FLAG_PHASE_LAUNCHES) {
+    if ((ps[i].flags ^ ps[0].flags) & (EC_FLAG_PHASE_LAUNCHES | EC_FLAG_ONE_LAUNCH)) {
       *why = "the systems of a batch share one schedule"; return EC_E_UNSUPPORTED;
     }
     bl->off[(size_t)i] = o;
@@ -849,7 +852,7 @@ ec_status ec_init_batch(const ec_params* ps, int32_t n_sys, void* ws, size_t ws_
   sh.n_sys = n_sys;
   sh.periodic = false;
   sh.fp32_screen = ps[0].precision == EC_PREC_FP32_SCREEN;
-  sh.one_launch = !(ps[0].flags & EC_FLAG_PHASE_LAUNCHES);
+  sh.one_launch = (ps[0].flags & EC_FLAG_ONE_LAUNCH) != 0;  // phase launches unless asked
   sh.cpb = 1;
   for (int32_t i = 0; i < n_sys; ++i) {
     ec_params p = ps[i];

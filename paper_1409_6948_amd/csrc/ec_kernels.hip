@@ -1060,6 +1060,8 @@ __global__ void __launch_bounds__(256) k_sweep_cells(const Dev* __restrict__ ds)
   const SweepDraws dr = *d.draws;
   const int half = d.C >> 1;
   const int per_phase = half * half;
+  // as many workers as one phase has cells (a batch launches for its largest system)
+  if (blockIdx.x * d.cells_per_block + wave >= per_phase) return;
   const int64_t epoch = sweep + 1;
   // phase of each colour, two bits per colour
   int phase_of = 0;

@@ -18,6 +18,7 @@ EC_PREC_FP64, EC_PREC_FP32_SCREEN = 0, 1
 EC_START_REPLACE, EC_START_DISTINCT = 0, 1
 EC_FLAG_SCAN_SEARCH = 1
 EC_FLAG_PHASE_LAUNCHES = 2
+EC_FLAG_ONE_LAUNCH = 4
 EC_ABI_VERSION = 1
 COUNT_NAMES = ("lifts", "frozen", "walls", "chains", "pseudo")
 

@@ -95,14 +95,17 @@ def test_batch_graph_and_schedule_keep_trajectories(P, cpb):
     b.close()
 
 
-def test_batch_phase_launches_equal_one_launch_solo_runs(P):
+def test_batch_one_launch_equals_solo_runs(P):
+    """The one-launch schedule forced on a batch (the batch default is one
+    launch per phase) follows the solo trajectories; systems smaller than the
+    largest leave their surplus wavefronts idle."""
     cfgs = inputs.batch_systems(64, seed=0)[:12]
     ps = _params(P, cfgs)
     sweeps = 2
-    _say("[batch] phase-launch schedule against one-launch solo runs")
+    _say("[batch] one-launch schedule against solo runs")
     solos = _solo_states(P, ps, sweeps)
     for p in ps:
-        p.flags |= P.EC_FLAG_PHASE_LAUNCHES
+        p.flags |= P.EC_FLAG_ONE_LAUNCH
     b = P.Batch(ps)
     b.set_graph(True)
     b.sweep(sweeps)
