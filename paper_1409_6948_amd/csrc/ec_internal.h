@@ -152,6 +152,9 @@ hipError_t launch_zero_tallies(const Dev* ds, int32_t n_cells, hipStream_t st);
 // Hexatic order parameter of one system (cutoff neighbours within r_cut,
 // r_cut <= cell side): rebin of the current sweep, per-disk Psi_k, and a
 // fixed-order reduction into psi_red.
+// Cell lists of the current grid (sweep draws, count, offsets, scatter), for
+// the observables of ec_observe.hip; one walled system.
+hipError_t launch_rebin(const Dev* ds, const LaunchShape& sh, hipStream_t st);
 hipError_t launch_psi6(const Dev* ds, const LaunchShape& sh, double r_cut, hipStream_t st);
 // Add the current configuration's ordered-pair counts (bins of width delta =
 // (r_max - sigma)/n_bins from sigma; r_max <= cell side) to gr_counts.

@@ -1255,170 +1255,6 @@ __global__ void k_zero_tallies(const Dev* __restrict__ ds) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// Hexatic order parameter (Sec. 2, eq. Psi) with cutoff neighbours.  One
-// thread per disk scans the 3 x 3 cells around its own (cutoff <= cell side,
-// so every neighbour is there), minimum image; exp(6 i phi) is computed as
-// ((dx + i dy)^2 / r^2)^3 with complex products and summed per disk in fixed
-// point.  Sums per block in a fixed order, then one block adds the block
-// sums in order: results repeat bit for bit.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void bond6(double dx, double dy, double r2, double& re, double& im) {
-  const double u = (dx * dx - dy * dy) / r2, v = (2.0 * dx * dy) / r2;
-  re = u * (u * u - 3.0 * v * v);
-  im = v * (3.0 * u * u - v * v);
-}
-
-__device__ __forceinline__ void psi6_block_sum(double re, double im, double nb, double* part) {
-  __shared__ double sh[3][256];
-  const int t = threadIdx.x;
-  sh[0][t] = re;
-  sh[1][t] = im;
-  sh[2][t] = nb;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (t < off) {
-      sh[0][t] = sh[0][t] + sh[0][t + off];
-      sh[1][t] = sh[1][t] + sh[1][t + off];
-      sh[2][t] = sh[2][t] + sh[2][t + off];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    part[3 * blockIdx.x] = sh[0][0];
-    part[3 * blockIdx.x + 1] = sh[1][0];
-    part[3 * blockIdx.x + 2] = sh[2][0];
-  }
-}
-
-__global__ void __launch_bounds__(256) k_psi6(const Dev* __restrict__ ds, double rc2) {
-  const Dev d = ds[blockIdx.y];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double re = 0.0, im = 0.0;
-  int nb = 0;
-  // bond terms in units of 2^-52 (|term| <= 1): integer sums do not depend on
-  // the order of the cell lists, which the atomic rebin leaves unspecified
-  long long fre = 0, fim = 0;
-  if (k < d.n) {
-    const double xk = d.x[k], yk = d.y[k];
-    const double L = d.L, half_L = d.half_L;
-    const int C = d.C;
-    const bool one_cell = C == 1;
-    const int c = one_cell ? 0 : d.cell_of[k];
-    const int cx = c % C, cy = c / C;
-    const int span = one_cell ? 0 : 1;
-    for (int oy = -span; oy <= span; ++oy) {
-      for (int ox = -span; ox <= span; ++ox) {
-        const int nc = ((cy + oy + C) % C) * C + (cx + ox + C) % C;
-        const int i0 = one_cell ? 0 : d.cell_start[nc];
-        const int i1 = one_cell ? (int)d.n : d.cell_start[nc + 1];
-        for (int i = i0; i < i1; ++i) {
-          const int l = one_cell ? i : d.cell_ids[i];
-          if (l == k) continue;
-          double dx = d.x[l] - xk, dy = d.y[l] - yk;
-          if (dx < -half_L) dx += L; else if (dx >= half_L) dx -= L;
-          if (dy < -half_L) dy += L; else if (dy >= half_L) dy -= L;
-          const double r2 = dx * dx + dy * dy;
-          if (r2 < rc2) {
-            double br, bi;
-            bond6(dx, dy, r2, br, bi);
-            fre += __double2ll_rn(br * 0x1p52);
-            fim += __double2ll_rn(bi * 0x1p52);
-            nb += 1;
-          }
-        }
-      }
-    }
-    if (nb > 0) {
-      re = ((double)fre * 0x1p-52) / (double)nb;
-      im = ((double)fim * 0x1p-52) / (double)nb;
-    }
-    d.psi[k] = make_double2(re, im);
-  }
-  psi6_block_sum(re, im, (double)nb, d.psi_part);
-}
-
-__global__ void __launch_bounds__(1024) k_psi6_final(const Dev* __restrict__ ds, int nblocks) {
-  const Dev d = ds[blockIdx.y];
-  __shared__ double sh[3][1024];
-  const int t = threadIdx.x;
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int i = t; i < nblocks; i += 1024) {
-    a = a + d.psi_part[3 * i];
-    b = b + d.psi_part[3 * i + 1];
-    c = c + d.psi_part[3 * i + 2];
-  }
-  sh[0][t] = a;
-  sh[1][t] = b;
-  sh[2][t] = c;
-  __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if (t < off) {
-      sh[0][t] = sh[0][t] + sh[0][t + off];
-      sh[1][t] = sh[1][t] + sh[1][t + off];
-      sh[2][t] = sh[2][t] + sh[2][t + off];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    const double n = (double)d.n;
-    d.psi_red[0] = sh[0][0] / n;
-    d.psi_red[1] = sh[1][0] / n;
-    d.psi_red[2] = sh[2][0] / n;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Pair histogram for the pressure route of eq. (pressure), Sec. 2: one thread
-// per disk scans the 3 x 3 cells around its own (r_max <= cell side), minimum
-// image, bin = floor((sqrt(dx*dx + dy*dy) - sigma) / delta).  Counts go to a
-// per-block LDS histogram, then to the global one (integers: exact and
-// independent of order).  Pairs closer than sigma are counted apart.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_gr(const Dev* __restrict__ ds, double r_max, double delta,
-                                            int n_bins) {
-  const Dev d = ds[blockIdx.y];
-  __shared__ unsigned int hist[kMaxGrBins + 1];
-  for (int i = threadIdx.x; i <= n_bins; i += blockDim.x) hist[i] = 0;
-  __syncthreads();
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < d.n) {
-    const double xk = d.x[k], yk = d.y[k];
-    const double L = d.L, half_L = d.half_L, r2max = r_max * r_max, sigma = d.sigma;
-    const int C = d.C;
-    const bool one_cell = C == 1;
-    const int c = one_cell ? 0 : d.cell_of[k];
-    const int cx = c % C, cy = c / C;
-    const int span = one_cell ? 0 : 1;
-    for (int oy = -span; oy <= span; ++oy) {
-      for (int ox = -span; ox <= span; ++ox) {
-        const int nc = ((cy + oy + C) % C) * C + (cx + ox + C) % C;
-        const int i0 = one_cell ? 0 : d.cell_start[nc];
-        const int i1 = one_cell ? (int)d.n : d.cell_start[nc + 1];
-        for (int i = i0; i < i1; ++i) {
-          const int l = one_cell ? i : d.cell_ids[i];
-          if (l == k) continue;
-          double dx = d.x[l] - xk, dy = d.y[l] - yk;
-          if (dx < -half_L) dx += L; else if (dx >= half_L) dx -= L;
-          if (dy < -half_L) dy += L; else if (dy >= half_L) dy -= L;
-          const double d2 = dx * dx + dy * dy;
-          if (!(d2 < r2max)) continue;
-          const double dist = sqrt(d2);
-          if (dist < sigma) {
-            atomicAdd(&hist[n_bins], 1u);
-            continue;
-          }
-          const double t = floor((dist - sigma) / delta);
-          if (t < (double)n_bins) atomicAdd(&hist[(int)t], 1u);
-        }
-      }
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i <= n_bins; i += blockDim.x)
-    if (hist[i]) atomicAdd(&d.gr_counts[i], (unsigned long long)hist[i]);
-}
-
 // The sweep counter every kernel of the next sweep reads (one thread per system).
 __global__ void k_sweep_done(const Dev* __restrict__ ds) {
   if (threadIdx.x == 0) *ds[blockIdx.y].sweep_ctr += 1;
@@ -1506,31 +1342,12 @@ hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
   return hipGetLastError();
 }
 
-hipError_t launch_psi6(const Dev* ds, const LaunchShape& sh, double r_cut, hipStream_t st) {
+hipError_t launch_rebin(const Dev* ds, const LaunchShape& sh, hipStream_t st) {
   const unsigned nblk = (unsigned)((sh.max_n + 255) / 256);
-  if (!sh.periodic) {
-    // cell lists of the current sweep's grid (the next sweep builds the same ones)
-    hipLaunchKernelGGL(k_prep, dim3(1, 1), dim3(1024), 0, st, ds);
-    hipLaunchKernelGGL(k_count, dim3(nblk, 1), dim3(256), 0, st, ds);
-    hipLaunchKernelGGL(k_scan, dim3(1, 1), dim3(1024), 0, st, ds);
-    hipLaunchKernelGGL(k_scatter, dim3(nblk, 1), dim3(256), 0, st, ds);
-  }
-  hipLaunchKernelGGL(k_psi6, dim3(nblk, 1), dim3(256), 0, st, ds, r_cut * r_cut);
-  hipLaunchKernelGGL(k_psi6_final, dim3(1, 1), dim3(1024), 0, st, ds, (int)nblk);
-  return hipGetLastError();
-}
-
-hipError_t launch_gr(const Dev* ds, const LaunchShape& sh, double r_max, double delta, int n_bins,
-                     hipStream_t st) {
-  const unsigned nblk = (unsigned)((sh.max_n + 255) / 256);
-  if (!sh.periodic) {
-    // cell lists of the current sweep's grid (the next sweep builds the same ones)
-    hipLaunchKernelGGL(k_prep, dim3(1, 1), dim3(1024), 0, st, ds);
-    hipLaunchKernelGGL(k_count, dim3(nblk, 1), dim3(256), 0, st, ds);
-    hipLaunchKernelGGL(k_scan, dim3(1, 1), dim3(1024), 0, st, ds);
-    hipLaunchKernelGGL(k_scatter, dim3(nblk, 1), dim3(256), 0, st, ds);
-  }
-  hipLaunchKernelGGL(k_gr, dim3(nblk, 1), dim3(256), 0, st, ds, r_max, delta, n_bins);
+  hipLaunchKernelGGL(k_prep, dim3(1, 1), dim3(1024), 0, st, ds);
+  hipLaunchKernelGGL(k_count, dim3(nblk, 1), dim3(256), 0, st, ds);
+  hipLaunchKernelGGL(k_scan, dim3(1, 1), dim3(1024), 0, st, ds);
+  hipLaunchKernelGGL(k_scatter, dim3(nblk, 1), dim3(256), 0, st, ds);
   return hipGetLastError();
 }
 
