@@ -563,3 +563,123 @@ def test_pair_histogram_single_pair_and_overlap():
     assert counts.sum() == 2 and counts[23] == 2
     assert ov == 2  # the pair at distance 0.5, both orders
     assert L > 10
+
+
+# ---- Delaunay Psi and its autocorrelation time (eq. Psi, eq. tau) --------------------------
+
+
+def _periodic_empty_circle_neighbours(x, y, L):
+    """Periodic Delaunay neighbours by definition: triangles of the 3 x 3 image
+    set with an empty circumcircle and at least one vertex in the box."""
+    from oracle import delaunay as D
+    n = len(x)
+    px = np.concatenate([x + sx * L for sx in (-1, 0, 1) for sy in (-1, 0, 1)])
+    py = np.concatenate([y + sy * L for sx in (-1, 0, 1) for sy in (-1, 0, 1)])
+    base = 4 * n  # (sx, sy) = (0, 0) comes fifth
+    p = np.stack([px, py], axis=1)
+    m = len(p)
+    nbrs = [set() for _ in range(n)]
+    for i in range(base, base + n):
+        for j in range(m):
+            if j == i:
+                continue
+            for k in range(j + 1, m):
+                if k == i:
+                    continue
+                a, b, c = p[i], p[j], p[k]
+                d = 2.0 * (a[0] * (b[1] - c[1]) + b[0] * (c[1] - a[1]) + c[0] * (a[1] - b[1]))
+                if abs(d) < 1e-12:
+                    continue
+                ux = ((a @ a) * (b[1] - c[1]) + (b @ b) * (c[1] - a[1]) + (c @ c) * (a[1] - b[1])) / d
+                uy = ((a @ a) * (c[0] - b[0]) + (b @ b) * (a[0] - c[0]) + (c @ c) * (b[0] - a[0])) / d
+                r2 = (a[0] - ux) ** 2 + (a[1] - uy) ** 2
+                if r2 > (0.5 * L) ** 2:
+                    continue  # a circle wider than the box is no triangle of the torus
+                dist2 = (p[:, 0] - ux) ** 2 + (p[:, 1] - uy) ** 2
+                dist2[[i, j, k]] = np.inf
+                if np.all(dist2 > r2):
+                    for q in (j, k):
+                        v = p[q] - p[i]
+                        nbrs[i - base].add((q % n, round(v[0], 9), round(v[1], 9)))
+    return nbrs
+
+
+def test_delaunay_library_step_matches_empty_circles():
+    """scipy's triangulation against the definition, plane and torus."""
+    from oracle import delaunay as D
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(11)
+    pts = rng.random((30, 2)) * 10.0
+    tri = Delaunay(pts)
+    lib = set()
+    for s in tri.simplices:
+        for a in range(3):
+            for b in range(a + 1, 3):
+                lib.add(tuple(sorted((int(s[a]), int(s[b])))))
+    assert lib == D.empty_circle_edges(pts[:, 0], pts[:, 1])
+    # periodic: 12 disks in a 6 x 6 box
+    L = 6.0
+    q = rng.random((12, 2)) * L
+    offsets, ids = D.delaunay_neighbours(q[:, 0], q[:, 1], L, L, margin=L)
+    got = [{(int(i), round(v[0], 9), round(v[1], 9)) for i, v in zip(idk, off)}
+           for idk, off in zip(ids, offsets)]
+    assert got == _periodic_empty_circle_neighbours(q[:, 0], q[:, 1], L)
+
+
+def test_delaunay_psi6_triangular_lattice():
+    """A periodic triangular lattice: six neighbours each, Psi_k = 1."""
+    from oracle import delaunay as D
+    nx, ny, a = 12, 14, 1.1
+    h = a * math.sqrt(3.0) / 2.0
+    x = np.array([(i + 0.5 * (j & 1)) * a for j in range(ny) for i in range(nx)])
+    y = np.array([j * h for j in range(ny) for i in range(nx)])
+    psi, per, counts = D.psi6_delaunay(x, y, nx * a, ny * h)
+    assert np.all(counts == 6)
+    np.testing.assert_allclose(per, 1.0, atol=1e-12)
+    assert abs(psi - 1.0) < 1e-12
+
+
+def test_delaunay_psi6_start_lattice_closed_form():
+    """The system's start lattice (rows offset by a/2) has a unique
+    triangulation: neighbours at (+-a, 0) and (+-a/2, +-a), so every
+    Psi_k = (2 + 4 cos(6 atan2(1, 1/2))) / 6, as with the cutoff neighbours."""
+    from oracle import delaunay as D
+    p = O.params(1024, 0.70, 20.0, 4)
+    x, y = O.lattice(p)
+    L = O.box_length(1024, 1.0, 0.70)
+    psi, per, counts = D.psi6_delaunay(x, y, L, L)
+    want = (2.0 + 4.0 * math.cos(6.0 * math.atan2(1.0, 0.5))) / 6.0
+    assert np.all(counts == 6)
+    np.testing.assert_allclose(per.real, want, atol=1e-12)
+    np.testing.assert_allclose(per.imag, 0.0, atol=1e-12)
+
+
+def test_delaunay_mean_degree_is_six_on_the_torus():
+    """Euler's relation on the torus (V - E + F = 0, 3F = 2E): mean degree 6."""
+    from oracle import delaunay as D
+    rng = np.random.default_rng(5)
+    for n, L in ((200, 14.0), (500, 22.0)):
+        q = rng.random((n, 2)) * L
+        _, _, counts = D.psi6_delaunay(q[:, 0], q[:, 1], L, L)
+        assert int(counts.sum()) == 6 * n
+
+
+def test_autocorrelation_closed_forms():
+    """Psi(t) = exp(i w t): C(dt) = cos(w dt); an exactly exponential C
+    returns its tau; an AR(1) series Psi(t+1) = a Psi(t) + noise has
+    C(dt) = a^dt, tau = -1 / ln a."""
+    from oracle import delaunay as D
+    w = 0.3
+    t = np.arange(400)
+    c = D.autocorrelation(np.exp(1j * w * t), 20)
+    np.testing.assert_allclose(c, np.cos(w * np.arange(21)), atol=1e-12)
+    assert abs(D.tau_fit(np.exp(-np.arange(30) / 4.5)) - 4.5) < 1e-12
+    rng = np.random.default_rng(3)
+    a, n = 0.9, 200000
+    noise = rng.normal(size=n) + 1j * rng.normal(size=n)
+    psi = np.empty(n, dtype=np.complex128)
+    psi[0] = noise[0]
+    for i in range(1, n):
+        psi[i] = a * psi[i - 1] + noise[i]
+    tau = D.tau_fit(D.autocorrelation(psi, 40))
+    assert abs(tau - (-1.0 / math.log(a))) / (-1.0 / math.log(a)) < 0.05
