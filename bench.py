@@ -13,6 +13,10 @@ shuffled list of distinct disks (N = 16384, eta = 0.70, 16 x 16 cells, seeds
 standard error over the seeds) and their difference in units of the combined
 error.
 
+With --workload psi6-delaunay it times the Delaunay-neighbour Psi at N = 1M;
+with --workload tau it reports the autocorrelation time (eq. tau) of 8
+seeded liquid systems from a Psi series.
+
 With --workload batch64 it times the batched form instead: the 64-system
 ensemble (N log-uniform in [4096, 262144], eta uniform in [0.30, 0.72], about
 64 disks per cell) advanced by shared launches, with the autotuned schedule
@@ -27,6 +31,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -124,6 +130,10 @@ def main():
         return bench_batch(args, torch, P)
     if args.workload == "start-rules":
         return bench_start_rules(args, torch, P)
+    if args.workload == "psi6-delaunay":
+        return bench_psi6_delaunay(args, torch, P)
+    if args.workload == "tau":
+        return bench_tau(args, torch, P)
     w = dict(inputs.WORKLOADS[args.workload])
     torch.cuda.set_device(0)
     prec = P.EC_PREC_FP64 if args.precision == "fp64" else P.EC_PREC_FP32_SCREEN
@@ -332,6 +342,54 @@ def bench_start_rules(args, torch, P):
     line = {"workload": "start-rules", "n_disks": n, "eta": eta, "cells_per_side": C, "ell": ell,
             "warmup": args.warmup, "sweeps": args.steps, "seconds": secs, "routes": out,
             "distinct_minus_replacement": diffs}
+    print(json.dumps(line), flush=True)
+
+def bench_psi6_delaunay(args, torch, P):
+    """Psi with Delaunay neighbours (eq. Psi) on the 1M-disk workload after one
+    sweep: time of one measurement (rebin, neighbour kernel, reduction, result
+    copy) with HIP events on the system's stream."""
+    w = dict(inputs.WORKLOADS["pec_1m"])
+    g = P.System(P.make_params(w["n"], w["eta"], w["ell"], w["cells"], dir_mode=w["dir_mode"],
+                               seed=w["seed"]), device="cuda:0")
+    g.sweep(1)
+    g.measure_psi6_delaunay()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(args.steps, 1)
+    e0.record(g.stream)
+    for _ in range(reps):
+        psi, nb = g.measure_psi6_delaunay()
+    e1.record(g.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    line = {"workload": "psi6-delaunay", "n_disks": w["n"], "eta": w["eta"], "measurements": reps,
+            "ms_per_measurement": ms, "disks_per_s": w["n"] / (ms / 1e3),
+            "psi_abs": abs(psi), "mean_neighbours": nb}
+    print(json.dumps(line), flush=True)
+
+
+def bench_tau(args, torch, P):
+    """The autocorrelation time tau of eq. (tau) in sweeps: 8 seeded liquid
+    systems (N = 16384, eta = 0.60, 16 x 16 cells) in one batch, Psi with
+    Delaunay neighbours after every sweep of the series."""
+    n, eta, C, seeds = 16384, 0.60, 16, 8
+    warm, series = max(args.warmup, 1) * 10, max(args.steps, 20) * 10
+    ps = [P.make_params(n, eta, 20.0, C, seed=sd + 1, system=sd) for sd in range(seeds)]
+    b = P.Batch(ps)
+    b.set_graph(True)
+    b.sweep(warm)
+    psis = np.zeros((seeds, series), dtype=np.complex128)
+    for t in range(series):
+        b.sweep(1)
+        for i, sy in enumerate(b.systems):
+            psis[i, t] = sy.measure_psi6_delaunay()[0]
+    b.close()
+    out = [P.psi_autocorrelation(psis[i], min(60, series - 1)) for i in range(seeds)]
+    line = {"workload": "tau", "n_disks": n, "eta": eta, "cells_per_side": C, "ell": 20.0,
+            "seeds": seeds, "warmup_sweeps": warm, "series_sweeps": series,
+            "tau_sweeps_per_seed": [t for _, t in out],
+            "c_lag1_per_seed": [float(c[1]) for c, _ in out],
+            "psi_abs_mean": float(np.mean(np.abs(psis)))}
     print(json.dumps(line), flush=True)
 
 if __name__ == "__main__":

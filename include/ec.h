@@ -155,6 +155,31 @@ ec_status ec_measure_pressure(ec_system sys, double* z, double* beta_p_sigma2, u
 ec_status ec_measure_psi6(ec_system sys, double r_cut, double* psi_re, double* psi_im,
                           double* mean_neighbours, double* per_disk);
 
+/* Psi with Delaunay neighbours, as eq. (Psi, Sec. 2) defines it: l is a
+ * neighbour of k iff the bisector of k and l bounds k's Voronoi cell, found
+ * on the device among the disks within r_search of k (<= 0: 4 L/sqrt(N), four
+ * mean spacings, about 50 candidates at any density, capped at the cell side).  The result is exact when every Voronoi vertex lies
+ * within r_search/2 of its disk, which is checked for every disk:
+ * EC_E_UNSUPPORTED (with ec_last_error) if some cell is not certified (raise
+ * r_search) or a disk has more than 128 candidates (lower it).  On a torus the
+ * mean neighbour count is 6.  Outputs as for ec_measure_psi6, plus
+ * neighbours[N] (may be NULL): each disk's count.  Configurations with four
+ * or more cocircular disks have several triangulations; this returns one.
+ * EC_E_INVALID if r_search exceeds the cell side (half the box for one
+ * periodic cell).  Synchronises. */
+ec_status ec_measure_psi6_delaunay(ec_system sys, double r_search, double* psi_re, double* psi_im,
+                                   double* mean_neighbours, double* per_disk, int32_t* neighbours);
+
+/* Autocorrelation of a time series of Psi (eq. tau, Sec. 2), host only:
+ * c[dt] = Re(sum_t conj(Psi_t) Psi_(t+dt) / (n - dt)) / (sum_t |Psi_t|^2 / n)
+ * for dt = 0..max_lag (c[0] = 1; the mean of Psi is taken as zero, its phase
+ * being arbitrary), and tau (may be NULL) from the least-squares fit of
+ * ln c[dt] = -dt / tau over dt = 1, 2, ... while c[dt] > e^-2 (NaN if
+ * c[1] <= e^-2).  EC_E_INVALID for n < 2, max_lag outside [1, n), a zero
+ * series or a NULL input. */
+ec_status ec_psi_autocorrelation(const double* psi_re, const double* psi_im, int64_t n,
+                                 int32_t max_lag, double* c, double* tau);
+
 /* ---- Pressure from the pair correlation at contact, eq. (pressure) of Sec. 2:
  * beta P sigma^2 = sigma^2 rho (1 + (pi/2) sigma^2 rho g(sigma+)).  Ordered pairs
  * (k, l), k != l, are counted in bins [e_i, e_i+1), e_i = sigma + i delta,

@@ -135,3 +135,28 @@ def tau_fit(c):
     d = np.array(d)
     lc = np.array(lc)
     return -float(np.sum(d * d) / np.sum(d * lc))
+
+
+def planar_neighbours(px, py, centre):
+    """Delaunay neighbours of point `centre` of a planar patch (offsets from it),
+    for sampling a large periodic system: the patch holds every disk within
+    some radius R of the centre (unwrapped), and the result is that of the
+    whole system when every triangle at the centre has its circumcircle
+    inside the patch's disk of radius R, which is checked."""
+    from scipy.spatial import Delaunay
+    p = np.stack([np.asarray(px, float), np.asarray(py, float)], axis=1)
+    R = np.sqrt(np.max(np.sum((p - p[centre]) ** 2, axis=1)))
+    tri = Delaunay(p)
+    s = tri.simplices[np.any(tri.simplices == centre, axis=1)]
+    a, b, c = p[s[:, 0]], p[s[:, 1]], p[s[:, 2]]
+    d = 2.0 * (a[:, 0] * (b[:, 1] - c[:, 1]) + b[:, 0] * (c[:, 1] - a[:, 1]) + c[:, 0] * (a[:, 1] - b[:, 1]))
+    aa, bb, cc = (a * a).sum(1), (b * b).sum(1), (c * c).sum(1)
+    ux = (aa * (b[:, 1] - c[:, 1]) + bb * (c[:, 1] - a[:, 1]) + cc * (a[:, 1] - b[:, 1])) / d
+    uy = (aa * (c[:, 0] - b[:, 0]) + bb * (a[:, 0] - c[:, 0]) + cc * (b[:, 0] - a[:, 0])) / d
+    r = np.sqrt((a[:, 0] - ux) ** 2 + (a[:, 1] - uy) ** 2)
+    dc = np.sqrt((ux - p[centre, 0]) ** 2 + (uy - p[centre, 1]) ** 2)
+    if np.any(dc + r > 0.999 * R):
+        raise ValueError("patch too small for the Delaunay triangles at its centre")
+    indptr, indices = tri.vertex_neighbor_vertices
+    nb = indices[indptr[centre]:indptr[centre + 1]]
+    return p[nb] - p[centre]

@@ -7,9 +7,10 @@ built library raises.
 """
 from .ec import (EC_DIR_ISOTROPIC, EC_DIR_X, EC_DIR_XY, EC_FLAG_ONE_LAUNCH, EC_FLAG_PHASE_LAUNCHES,
                  EC_FLAG_SCAN_SEARCH, EC_PREC_FP32_SCREEN, EC_PREC_FP64, EC_START_DISTINCT, EC_START_REPLACE, Batch, ECError, System, batch_workspace_bytes,
-                 gr_normalize, lib_path, load_library, make_params, workspace_bytes)
+                 gr_normalize, lib_path, load_library, make_params, psi_autocorrelation,
+                 workspace_bytes)
 
 __all__ = ["EC_DIR_ISOTROPIC", "EC_DIR_X", "EC_DIR_XY", "EC_FLAG_ONE_LAUNCH", "EC_FLAG_PHASE_LAUNCHES",
            "EC_FLAG_SCAN_SEARCH", "EC_PREC_FP32_SCREEN", "EC_PREC_FP64", "EC_START_DISTINCT", "EC_START_REPLACE", "Batch", "ECError", "System",
            "batch_workspace_bytes", "gr_normalize", "lib_path", "load_library", "make_params",
-           "workspace_bytes"]
+           "psi_autocorrelation", "workspace_bytes"]

@@ -21,7 +21,7 @@ constexpr double kPi = 3.14159265358979323846;
 struct Layout {
   size_t dev, sweep_ctr, x, y, cell_of, cell_ids, cell_count, cell_fill, cell_start, acc_delta, acc_cnt,
       ring, cell_digest, draws, err, red, chain_start, chain_dir, shuffle, dbg, psi, psi_part, psi_red,
-      gr, queue, cell_done, total;
+      gr, queue, cell_done, psi_nb, psi_err, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -62,6 +62,8 @@ Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell) {
   l.gr = o;         o = align256(o + 8 * (size_t)(ec::kMaxGrBins + 1));
   l.queue = o;      o = align256(o + 8);
   l.cell_done = o;  o = align256(o + 8 * nc);
+  l.psi_nb = o;     o = align256(o + 4 * (size_t)n);
+  l.psi_err = o;    o = align256(o + 16);
   l.total = o;
   return l;
 }
@@ -314,6 +316,8 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   d.gr_counts = (unsigned long long*)(b + lay.gr);
   d.queue = (int32_t*)(b + lay.queue);
   d.cell_done = (int64_t*)(b + lay.cell_done);
+  d.psi_nb = (int32_t*)(b + lay.psi_nb);
+  d.psi_err = (unsigned long long*)(b + lay.psi_err);
   d.dep_wait_ticks = kDefaultDepWaitTicks;
   d.search = (p->flags & EC_FLAG_SCAN_SEARCH) ? 1 : 0;
   d.n = p->n_disks;
@@ -502,6 +506,79 @@ ec_status ec_measure_psi6(ec_system s, double r_cut, double* psi_re, double* psi
   if (psi_re) *psi_re = red[0];
   if (psi_im) *psi_im = red[1];
   if (mean_neighbours) *mean_neighbours = red[2];
+  return EC_OK;
+}
+
+ec_status ec_measure_psi6_delaunay(ec_system s, double r_search, double* psi_re, double* psi_im,
+                                   double* mean_neighbours, double* per_disk, int32_t* neighbours) {
+  if (!s || !std::isfinite(r_search)) return EC_E_INVALID;
+  const double spacing = s->dv.L / std::sqrt((double)s->p.n_disks);
+  const double rs = r_search > 0.0 ? r_search : std::min(4.0 * spacing, s->p.cells_per_side == 1 ? 0.5 * s->dv.L : s->dv.w);
+  const double limit = s->p.cells_per_side == 1 ? 0.5 * s->dv.L : s->dv.w;
+  if (!(rs <= limit) || s->p.n_disks < 3) {
+    s->last_error = "r_search must not exceed the cell side (half the box for one periodic cell)";
+    return EC_E_INVALID;
+  }
+  EC_HIP(s, ec::launch_psi6_delaunay(s->dev_d, s->shape, rs, s->stream));
+  double red[3];
+  unsigned long long bad[2];
+  EC_HIP(s, hipMemcpyAsync(red, s->dev.psi_red, sizeof red, hipMemcpyDeviceToHost, s->stream));
+  EC_HIP(s, hipMemcpyAsync(bad, s->dev.psi_err, sizeof bad, hipMemcpyDeviceToHost, s->stream));
+  if (per_disk)
+    EC_HIP(s, hipMemcpyAsync(per_disk, s->dev.psi, 16 * (size_t)s->p.n_disks, hipMemcpyDeviceToHost,
+                             s->stream));
+  if (neighbours)
+    EC_HIP(s, hipMemcpyAsync(neighbours, s->dev.psi_nb, 4 * (size_t)s->p.n_disks,
+                             hipMemcpyDeviceToHost, s->stream));
+  ec_status st = check_err(s);
+  if (st != EC_OK) return st;
+  if (bad[0] || bad[1]) {
+    char buf[256];
+    std::string why = "Delaunay neighbours not certified at r_search = ";
+    std::snprintf(buf, sizeof buf, "%.6g:", rs);
+    why += buf;
+    if (bad[0]) {
+      std::snprintf(buf, sizeof buf, " %llu disks with a Voronoi vertex beyond r_search/2 (raise r_search);", bad[0]);
+      why += buf;
+    }
+    if (bad[1]) {
+      std::snprintf(buf, sizeof buf, " %llu disks with more than 128 candidates (lower r_search);", bad[1]);
+      why += buf;
+    }
+    s->last_error = why;
+    return EC_E_UNSUPPORTED;
+  }
+  if (psi_re) *psi_re = red[0];
+  if (psi_im) *psi_im = red[1];
+  if (mean_neighbours) *mean_neighbours = red[2];
+  return EC_OK;
+}
+
+ec_status ec_psi_autocorrelation(const double* psi_re, const double* psi_im, int64_t n,
+                                 int32_t max_lag, double* c, double* tau) {
+  if (!psi_re || !psi_im || !c || n < 2 || max_lag < 1 || max_lag >= n) return EC_E_INVALID;
+  // eq. (tau): C(dt) = Re <Psi*(t) Psi(t + dt)>_t / <|Psi(t)|^2>_t
+  double den = 0.0;
+  for (int64_t t = 0; t < n; ++t) den += psi_re[t] * psi_re[t] + psi_im[t] * psi_im[t];
+  den /= (double)n;
+  if (!(den > 0.0)) return EC_E_INVALID;
+  for (int32_t lag = 0; lag <= max_lag; ++lag) {
+    double acc = 0.0;
+    for (int64_t t = 0; t + lag < n; ++t)  // Re(conj(a) b) = ar br + ai bi
+      acc += psi_re[t] * psi_re[t + lag] + psi_im[t] * psi_im[t + lag];
+    c[lag] = acc / (double)(n - lag) / den;
+  }
+  if (tau) {
+    // ln C(dt) = -dt / tau by least squares through the origin, dt = 1, 2, ...
+    // while C(dt) > e^-2
+    double sdd = 0.0, sdl = 0.0;
+    for (int32_t lag = 1; lag <= max_lag; ++lag) {
+      if (!(c[lag] > std::exp(-2.0))) break;
+      sdd += (double)lag * (double)lag;
+      sdl += (double)lag * std::log(c[lag]);
+    }
+    *tau = sdd > 0.0 ? -sdd / sdl : std::nan("");
+  }
   return EC_OK;
 }
 

@@ -70,6 +70,8 @@ struct Dev {
   double2* psi;                     // [N] per-disk hexatic order Psi_k (re, im)
   double* psi_part;                 // [3 * ceil(N/256)] per-block sums (re, im, neighbours)
   double* psi_red;                  // [3] Psi (re, im) and the mean neighbour count
+  int32_t* psi_nb;                  // [N] Delaunay neighbour count of each disk
+  unsigned long long* psi_err;      // [2] disks whose Voronoi cell was not certified; candidate overflows
   unsigned long long* gr_counts;    // [kMaxGrBins + 1] pair counts per bin, then pairs < sigma
   int32_t* queue;                   // [1] ticket counter of the one-launch sweep
   int64_t* cell_done;               // [C*C] last sweep + 1 whose write-back the cell has published
@@ -158,6 +160,9 @@ hipError_t launch_rebin(const Dev* ds, const LaunchShape& sh, hipStream_t st);
 hipError_t launch_psi6(const Dev* ds, const LaunchShape& sh, double r_cut, hipStream_t st);
 // Add the current configuration's ordered-pair counts (bins of width delta =
 // (r_max - sigma)/n_bins from sigma; r_max <= cell side) to gr_counts.
+// Psi with Delaunay neighbours: candidates within r_search, Voronoi cells
+// certified within r_search / 2.
+hipError_t launch_psi6_delaunay(const Dev* ds, const LaunchShape& sh, double r_search, hipStream_t st);
 hipError_t launch_gr(const Dev* ds, const LaunchShape& sh, double r_max, double delta, int n_bins,
                      hipStream_t st);
 

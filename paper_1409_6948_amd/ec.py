@@ -30,6 +30,7 @@ EXPORTED = ("ec_workspace_bytes", "ec_init_system", "ec_sweep", "ec_measure_pres
             "ec_last_error", "ec_batch_workspace_bytes", "ec_init_batch", "ec_sweep_batch",
             "ec_batch_system", "ec_batch_set_graph", "ec_batch_set_cells_per_block",
             "ec_batch_autotune", "ec_batch_last_error", "ec_destroy_batch", "ec_measure_psi6",
+            "ec_measure_psi6_delaunay", "ec_psi_autocorrelation",
             "ec_gr_accumulate", "ec_gr_counts", "ec_gr_reset", "ec_gr_normalize")
 
 
@@ -72,6 +73,8 @@ def load_library():
         "ec_sweep": [vp, C.c_int64],
         "ec_measure_pressure": [vp, dp, dp, u64p],
         "ec_measure_psi6": [vp, C.c_double, dp, dp, dp, dp],
+        "ec_measure_psi6_delaunay": [vp, C.c_double, dp, dp, dp, dp, C.POINTER(C.c_int32)],
+        "ec_psi_autocorrelation": [dp, dp, C.c_int64, C.c_int32, dp, dp],
         "ec_gr_accumulate": [vp, C.c_double, C.c_int32],
         "ec_gr_counts": [vp, u64p, C.POINTER(C.c_int64), u64p],
         "ec_gr_reset": [vp],
@@ -186,6 +189,20 @@ class System:
                self.h, "ec_measure_psi6")
         out = (complex(re.value, im.value), nb.value)
         return out + (per[0::2] + 1j * per[1::2],) if per_disk else out
+
+    def measure_psi6_delaunay(self, r_search=0.0, per_disk=False):
+        """Hexatic order parameter with Delaunay neighbours: (Psi, mean neighbour
+        count[, per-disk Psi_k as a complex array, per-disk neighbour counts])."""
+        re, im, nb = C.c_double(), C.c_double(), C.c_double()
+        per = np.zeros(2 * self.n, dtype=np.float64) if per_disk else None
+        cnt = np.zeros(self.n, dtype=np.int32) if per_disk else None
+        _check(self._lib.ec_measure_psi6_delaunay(
+            self.h, float(r_search), C.byref(re), C.byref(im), C.byref(nb),
+            _dptr(per) if per_disk else None,
+            cnt.ctypes.data_as(C.POINTER(C.c_int32)) if per_disk else None),
+            self.h, "ec_measure_psi6_delaunay")
+        out = (complex(re.value, im.value), nb.value)
+        return out + (per[0::2] + 1j * per[1::2], cnt) if per_disk else out
 
     def gr_accumulate(self, r_max, n_bins):
         """Add the current configuration's ordered-pair counts to the histogram."""
@@ -335,6 +352,20 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def psi_autocorrelation(psi, max_lag):
+    """C(dt) for dt = 0..max_lag and the fitted decay time tau of a complex
+    time series of Psi (ec_psi_autocorrelation, eq. tau)."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    re = np.ascontiguousarray(psi.real)
+    im = np.ascontiguousarray(psi.imag)
+    c = np.zeros(int(max_lag) + 1)
+    tau = C.c_double()
+    _check(load_library().ec_psi_autocorrelation(_dptr(re), _dptr(im), len(psi), int(max_lag),
+                                                 _dptr(c), C.byref(tau)),
+           what="ec_psi_autocorrelation")
+    return c, tau.value
 
 
 def gr_normalize(n_disks, box, sigma, r_max, counts, samples, fit_width=0.05):

@@ -1,9 +1,11 @@
 """Host-side checks of the C ABI: the library loads, exports every symbol
 declared in include/ec.h, and rejects invalid parameters (no GPU needed)."""
 import ctypes as C
+import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1409_6948_amd as P
@@ -142,3 +144,27 @@ def test_gr_normalize_rejects_bad_arguments():
         P.gr_normalize(4096, 80.0, 1.0, 1.5, c, 0)       # no samples
     with pytest.raises(E.ECError):
         P.gr_normalize(4096, 80.0, 1.0, 1.5, c, 1, 0.01)  # fewer than 3 bins in the fit
+
+
+def test_psi_autocorrelation_matches_oracle():
+    """ec_psi_autocorrelation against the oracle's eq. (tau) on an AR(1)
+    series, the closed form cos(w dt) of a rotating phase, and rejections."""
+    from oracle import delaunay as D
+    rng = np.random.default_rng(4)
+    n, a = 20000, 0.8
+    noise = rng.normal(size=n) + 1j * rng.normal(size=n)
+    psi = np.empty(n, dtype=np.complex128)
+    psi[0] = noise[0]
+    for i in range(1, n):
+        psi[i] = a * psi[i - 1] + noise[i]
+    c, tau = P.psi_autocorrelation(psi, 30)
+    np.testing.assert_allclose(c, D.autocorrelation(psi, 30), rtol=1e-12, atol=1e-12)
+    assert abs(tau - D.tau_fit(D.autocorrelation(psi, 30))) < 1e-9
+    c2, _ = P.psi_autocorrelation(np.exp(0.3j * np.arange(500)), 10)
+    np.testing.assert_allclose(c2, np.cos(0.3 * np.arange(11)), atol=1e-12)
+    _, tau3 = P.psi_autocorrelation(rng.normal(size=1000) + 0j, 5)  # white noise: no decay time
+    assert math.isnan(tau3)
+    for bad in ((psi[:1], 1), (psi, 0), (psi[:10], 10), (np.zeros(10, complex), 3)):
+        with pytest.raises(E.ECError) as ei:
+            P.psi_autocorrelation(*bad)
+        assert ei.value.status == E.EC_E_INVALID

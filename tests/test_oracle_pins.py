@@ -683,3 +683,24 @@ def test_autocorrelation_closed_forms():
         psi[i] = a * psi[i - 1] + noise[i]
     tau = D.tau_fit(D.autocorrelation(psi, 40))
     assert abs(tau - (-1.0 / math.log(a))) / (-1.0 / math.log(a)) < 0.05
+
+
+def test_delaunay_planar_patch_equals_periodic():
+    """Neighbours of sampled disks from a planar patch equal those of the
+    periodic triangulation."""
+    from oracle import delaunay as D
+    rng = np.random.default_rng(8)
+    L, n = 30.0, 700
+    q = rng.random((n, 2)) * L
+    offsets, _ = D.delaunay_neighbours(q[:, 0], q[:, 1], L, L)
+    for k in (0, 17, 333):
+        dx = q[:, 0] - q[k, 0]
+        dy = q[:, 1] - q[k, 1]
+        dx -= L * np.round(dx / L)
+        dy -= L * np.round(dy / L)
+        sel = np.nonzero(dx * dx + dy * dy < 8.0 ** 2)[0]
+        centre = int(np.nonzero(sel == k)[0][0])
+        got = D.planar_neighbours(dx[sel], dy[sel], centre)
+        a = sorted(map(tuple, np.round(got, 9)))
+        b = sorted(map(tuple, np.round(offsets[k], 9)))
+        assert a == b
