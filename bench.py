@@ -13,6 +13,10 @@ shuffled list of distinct disks (N = 16384, eta = 0.70, 16 x 16 cells, seeds
 standard error over the seeds) and their difference in units of the combined
 error.
 
+With --workload nm-scan it compares the pressure against n_m for both start
+rules (Fig. 3 right); --workload serial-ref compares PEC with serial EC of
+the same N.
+
 With --workload psi6-delaunay it times the Delaunay-neighbour Psi at N = 1M;
 with --workload tau it reports the autocorrelation time (eq. tau) of 8
 seeded liquid systems from a Psi series.
@@ -130,6 +134,10 @@ def main():
         return bench_batch(args, torch, P)
     if args.workload == "start-rules":
         return bench_start_rules(args, torch, P)
+    if args.workload == "serial-ref":
+        return bench_serial_ref(args, torch, P)
+    if args.workload == "nm-scan":
+        return bench_nm_scan(args, torch, P)
     if args.workload == "psi6-delaunay":
         return bench_psi6_delaunay(args, torch, P)
     if args.workload == "tau":
@@ -390,6 +398,153 @@ def bench_tau(args, torch, P):
             "tau_sweeps_per_seed": [t for _, t in out],
             "c_lag1_per_seed": [float(c[1]) for c, _ in out],
             "psi_abs_mean": float(np.mean(np.abs(psis)))}
+    print(json.dumps(line), flush=True)
+
+def _z_routes(P, sysm, n, box, r_max=1.5, n_bins=100, fit=0.05):
+    counts, samples, _ = sysm.gr_counts()
+    return sysm.measure_pressure()[0], P.gr_normalize(n, box, 1.0, r_max, counts, samples, fit)[3]
+
+
+def bench_serial_ref(args, torch, P):
+    """PEC against serial EC in one periodic cell of the same N (the exact
+    reference): N = 256, eta = 0.70, 4 x 4 cells (16 disks each), both start
+    rules at n_m = 1, 4, 16, 16 seeds per case, both pressure routes.  Every
+    case runs about the same number of chains: 16 / n_m times as many sweeps
+    as n_m = 16."""
+    import math
+    n, eta, ell, seeds = 256, 0.70, 20.0, 16
+    box = math.sqrt(n * math.pi / (4.0 * eta))
+    base_warm, base_sweeps = max(args.warmup, 1) * 2, max(args.steps, 1) * 5
+
+    def stats(v):
+        m = sum(v) / len(v)
+        return m, math.sqrt(sum((x - m) ** 2 for x in v) / (len(v) - 1) / len(v))
+
+    t0 = time.perf_counter()
+    # serial reference: one periodic cell, every disk starts one chain per sweep
+    serial = []
+    for sd in range(seeds):
+        st = torch.cuda.Stream()
+        g = P.System(P.make_params(n, eta, ell, 1, dir_mode=P.EC_DIR_ISOTROPIC, seed=sd + 1), stream=st)
+        serial.append(g)
+    for g in serial:
+        g.sweep(base_warm)
+    torch.cuda.synchronize()
+    for g in serial:
+        g.reset_tallies()
+        g.gr_reset()
+    for t in range(base_sweeps):
+        for g in serial:
+            g.sweep(1)
+            g.gr_accumulate(1.5, 100)
+        if t % 50 == 49:
+            torch.cuda.synchronize()
+            print(f"# serial-ref: serial sweep {t + 1} ({time.perf_counter() - t0:.1f} s)",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    zs = [_z_routes(P, g, n, box) for g in serial]
+    ref = {"ec": stats([z[0] for z in zs]), "gr_contact": stats([z[1] for z in zs])}
+    print(f"# serial-ref: serial reference done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+          flush=True)
+    cases = []
+    for nm in (1, 4, 16):
+        scale = 16 // nm
+        ps = []
+        for rule in (P.EC_START_REPLACE, P.EC_START_DISTINCT):
+            for sd in range(seeds):
+                ps.append(P.make_params(n, eta, ell, 4, seed=sd + 1, chains_per_cell=nm, start_mode=rule,
+                                        system=len(ps)))
+        b = P.Batch(ps)
+        b.set_graph(True)
+        b.sweep(base_warm * scale)
+        b.stream.synchronize()
+        for sy in b.systems:
+            sy.reset_tallies()
+            sy.gr_reset()
+        for _ in range(base_sweeps * scale):
+            b.sweep(1)
+            for sy in b.systems:
+                sy.gr_accumulate(1.5, 100)
+        b.stream.synchronize()
+        zs = [_z_routes(P, sy, n, box) for sy in b.systems]
+        b.close()
+        for r, rule in enumerate(("replacement", "distinct")):
+            part = zs[r * seeds:(r + 1) * seeds]
+            c = {"n_m": nm, "rule": rule, "sweeps": base_sweeps * scale}
+            for k, route in enumerate(("ec", "gr_contact")):
+                m, se = stats([z[k] for z in part])
+                rm, rse = ref[route]
+                c[route] = {"z_mean": m, "z_stderr": se,
+                            "minus_serial_in_stderr": (m - rm) / math.hypot(se, rse)}
+            cases.append(c)
+        print(f"# serial-ref: n_m = {nm} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+              flush=True)
+    line = {"workload": "serial-ref", "n_disks": n, "eta": eta, "cells_per_side": 4, "ell": ell,
+            "seeds": seeds, "serial_sweeps": base_sweeps, "warmup_sweeps_per_n_m_16": base_warm,
+            "serial": {r: {"z_mean": v[0], "z_stderr": v[1]} for r, v in ref.items()},
+            "pec": cases, "seconds": time.perf_counter() - t0}
+    print(json.dumps(line), flush=True)
+
+def bench_nm_scan(args, torch, P):
+    """Pressure against the list length n_m for both start rules (Sec. 3.4,
+    Fig. 3 right): N = 16384, eta = 0.70, 16 x 16 cells (about 64 disks each),
+    n_m = 1, 4, 16, 64, 8 seeds per case, both pressure routes.  At n_m = 1 the
+    two rules draw from the same distribution, the paper's reference.  Every
+    case runs the same number of chains (64 / n_m times the sweeps of
+    n_m = 64) and the same number of g(r) samples."""
+    import math
+    n, eta, ell, C, seeds = 16384, 0.70, 20.0, 16, 8
+    box = math.sqrt(n * math.pi / (4.0 * eta))
+    warm, meas = max(args.warmup, 1) * 10, max(args.steps, 1) * 5
+
+    def stats(v):
+        m = sum(v) / len(v)
+        return m, math.sqrt(sum((x - m) ** 2 for x in v) / (len(v) - 1) / len(v))
+
+    t0 = time.perf_counter()
+    cases = {}
+    for nm in (1, 4, 16, 64):
+        scale = 64 // nm
+        ps = []
+        for rule in (P.EC_START_REPLACE, P.EC_START_DISTINCT):
+            for sd in range(seeds):
+                ps.append(P.make_params(n, eta, ell, C, seed=sd + 1, chains_per_cell=nm, start_mode=rule,
+                                        system=len(ps)))
+        b = P.Batch(ps)
+        b.set_graph(True)
+        b.sweep(warm * scale)
+        b.stream.synchronize()
+        for sy in b.systems:
+            sy.reset_tallies()
+            sy.gr_reset()
+        for _ in range(meas):
+            b.sweep(scale)
+            for sy in b.systems:
+                sy.gr_accumulate(1.5, 100)
+        b.stream.synchronize()
+        zs = [_z_routes(P, sy, n, box) for sy in b.systems]
+        b.close()
+        for r, rule in enumerate(("replacement", "distinct")):
+            part = zs[r * seeds:(r + 1) * seeds]
+            cases[(nm, rule)] = {route: stats([z[k] for z in part])
+                                 for k, route in enumerate(("ec", "gr_contact"))}
+        print(f"# nm-scan: n_m = {nm} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+              flush=True)
+    # reference: n_m = 1, both rules pooled (the same distribution)
+    out = []
+    for (nm, rule), v in sorted(cases.items()):
+        c = {"n_m": nm, "rule": rule, "sweeps": meas * 64 // nm}
+        for route in ("ec", "gr_contact"):
+            m, se = v[route]
+            r1, r2 = cases[(1, "replacement")][route], cases[(1, "distinct")][route]
+            rm = 0.5 * (r1[0] + r2[0])
+            rse = 0.5 * math.hypot(r1[1], r2[1])
+            c[route] = {"z_mean": m, "z_stderr": se,
+                        "minus_n_m_1_in_stderr": (m - rm) / math.hypot(se, rse) if nm > 1 else None}
+        out.append(c)
+    line = {"workload": "nm-scan", "n_disks": n, "eta": eta, "cells_per_side": C, "ell": ell,
+            "seeds": seeds, "warmup_sweeps_at_n_m_64": warm, "sweeps_at_n_m_64": meas,
+            "cases": out, "seconds": time.perf_counter() - t0}
     print(json.dumps(line), flush=True)
 
 if __name__ == "__main__":
