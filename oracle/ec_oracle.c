@@ -240,7 +240,24 @@ typedef struct {
   uint64_t* acc_cnt;
   uint64_t digest;
   uint64_t n_events;       /* events of this cell so far in the phase (digest index) */
+  int reject;              /* ORC_BOUNDARY_REJECT: a wall or frozen event undoes the chain */
+  int64_t u_n, u_cap;      /* undo log of the running chain: disk, position before a move */
+  int64_t* u_a;
+  double *u_x, *u_y;
 } chain_ctx;
+
+static void undo_push(chain_ctx* cx, int64_t a) {
+  if (cx->u_n == cx->u_cap) {
+    cx->u_cap = cx->u_cap ? 2 * cx->u_cap : 64;
+    cx->u_a = (int64_t*)realloc(cx->u_a, sizeof(int64_t) * (size_t)cx->u_cap);
+    cx->u_x = (double*)realloc(cx->u_x, sizeof(double) * (size_t)cx->u_cap);
+    cx->u_y = (double*)realloc(cx->u_y, sizeof(double) * (size_t)cx->u_cap);
+  }
+  cx->u_a[cx->u_n] = a;
+  cx->u_x[cx->u_n] = cx->ox[a];
+  cx->u_y[cx->u_n] = cx->oy[a];
+  cx->u_n += 1;
+}
 
 static void digest_event(chain_ctx* cx, int kind, int64_t gid, double s) {
   uint64_t sb;
@@ -289,6 +306,10 @@ static void run_chain(chain_ctx* cx, int64_t a, double dx, double dy, double ell
   double idx = (dx != 0.0) ? 1.0 / dx : 0.0;
   double idy = (dy != 0.0) ? 1.0 / dy : 0.0;
   cx->acc_cnt[ORC_CNT_CHAINS] += 1;
+  /* rejection variant: the chain's lifts and contact sum count only if it is accepted */
+  double chain_delta = 0.0;
+  uint64_t chain_lifts = 0;
+  cx->u_n = 0;
   for (;;) {
     double ax = cx->ox[a], ay = cx->oy[a];
     /* brute-force search for the first event: key (s, id), lowest id wins ties */
@@ -347,9 +368,14 @@ static void run_chain(chain_ctx* cx, int64_t a, double dx, double dy, double ell
       move_by(cx, a, rem, dx, dy);
       log_event(cx, ORC_EV_END, cx->n + 3, cx->ogid[a], rem, dx, dy, cx->ox[a], cx->oy[a], NAN,
                 NAN);
+      if (cx->reject) {  /* accepted */
+        cx->acc_delta[0] += chain_delta;
+        cx->acc_cnt[ORC_CNT_LIFTS] += chain_lifts;
+      }
       break;
     }
     digest_event(cx, best_kind, best_gid, best_s);
+    if (cx->reject) undo_push(cx, a);
     move_by(cx, a, best_s, dx, dy);
     rem = rem - best_s;
     ax = cx->ox[a]; ay = cx->oy[a];
@@ -359,12 +385,27 @@ static void run_chain(chain_ctx* cx, int64_t a, double dx, double dy, double ell
       if (best_kind == ORC_EV_FROZEN) { px = cx->hx[best_j]; py = cx->hy[best_j]; }
       log_event(cx, best_kind, best_gid, cx->ogid[a], best_s, dx, dy, ax, ay, px, py);
     }
+    if (cx->reject && best_kind != ORC_EV_LIFT) {
+      /* a wall or a frozen disk: the whole chain is rejected -- every move is
+       * undone, latest first; the event that caused it is counted */
+      cx->acc_cnt[best_kind == ORC_EV_FROZEN ? ORC_CNT_FROZEN : ORC_CNT_WALLS] += 1;
+      for (int64_t u = cx->u_n - 1; u >= 0; --u) {
+        cx->ox[cx->u_a[u]] = cx->u_x[u];
+        cx->oy[cx->u_a[u]] = cx->u_y[u];
+      }
+      break;
+    }
     if (best_kind == ORC_EV_LIFT) {
       /* straight EC: the hit disk continues along the same direction */
       double rx = cx->ox[best_j] - ax, ry = cx->oy[best_j] - ay;
       if (cx->periodic) { rx = min_image(rx, cx); ry = min_image(ry, cx); }
-      cx->acc_delta[0] += fma(rx, dx, ry * dy);
-      cx->acc_cnt[ORC_CNT_LIFTS] += 1;
+      if (cx->reject) {
+        chain_delta = chain_delta + fma(rx, dx, ry * dy);
+        chain_lifts += 1;
+      } else {
+        cx->acc_delta[0] += fma(rx, dx, ry * dy);
+        cx->acc_cnt[ORC_CNT_LIFTS] += 1;
+      }
       a = best_j;
     } else if (best_kind == ORC_EV_FROZEN) {
       /* specular reflection about the contact normal */
@@ -428,6 +469,7 @@ static int check_params(const orc_params* p) {
   double L = orc_box_length(p->n, p->sigma, p->eta);
   if (p->cells == 1 && !(L > 2.0 * p->sigma)) return -1;
   if (p->cells > 1 && !(L / (double)p->cells > p->sigma)) return -1;
+  if (p->boundary > ORC_BOUNDARY_REJECT || (p->boundary == ORC_BOUNDARY_REJECT && p->cells == 1)) return -1;
   return 0;
 }
 
@@ -551,6 +593,7 @@ static void run_cell(const orc_params* p, double* x, double* y, int64_t sweep, i
   cx.acc_cnt = &acc_cnt[(int64_t)cell * ORC_CNT_NCOL];
   cx.digest = 0;
   cx.n_events = 0;
+  cx.reject = p->boundary == ORC_BOUNDARY_REJECT;
 
   int64_t n_m = 0;
   if (n_c > 0) n_m = p->chains_per_cell > 0 ? p->chains_per_cell : n_c;
@@ -572,6 +615,7 @@ static void run_cell(const orc_params* p, double* x, double* y, int64_t sweep, i
   }
   *cell_digest = cx.digest;
   free(starts); free(hx); free(hy); free(hg); free(vx); free(vy); free(vx0); free(vy0);
+  free(cx.u_a); free(cx.u_x); free(cx.u_y);
 }
 
 /* id-ordered own lists of all cells: counting sort of disks by cell. */

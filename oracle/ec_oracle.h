@@ -22,6 +22,10 @@ extern "C" {
 
 enum { ORC_DIR_XY = 0, ORC_DIR_ISO = 1, ORC_DIR_X = 2 };
 enum { ORC_START_REPLACE = 0, ORC_START_DISTINCT = 1 };
+/* What a chain does at a cell wall or a frozen disk (walled cells): reflect
+ * with equal angles (Sec. 3.4, Fig. 1 right), or reject the whole chain,
+ * the variant of Sec. 3.4 attributed to the striped decomposition. */
+enum { ORC_BOUNDARY_REFLECT = 0, ORC_BOUNDARY_REJECT = 1 };
 
 /* Event kinds, also used in the event digest. */
 enum { ORC_EV_LIFT = 1, ORC_EV_FROZEN = 2, ORC_EV_WALL_X = 3, ORC_EV_WALL_Y = 4,
@@ -42,7 +46,7 @@ typedef struct {
   int32_t  start_mode;      /* ORC_START_*                                        */
   uint64_t seed;
   uint32_t system;          /* index of the system inside a batch (RNG key)      */
-  uint32_t pad;
+  uint32_t boundary;        /* ORC_BOUNDARY_* (walled cells)                      */
 } orc_params;
 
 /* Optional event log (small systems only). */

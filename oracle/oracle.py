@@ -13,6 +13,7 @@ from . import build as _build
 
 DIR_XY, DIR_ISO, DIR_X = 0, 1, 2
 START_REPLACE, START_DISTINCT = 0, 1
+BOUNDARY_REFLECT, BOUNDARY_REJECT = 0, 1
 EV_LIFT, EV_FROZEN, EV_WALL_X, EV_WALL_Y, EV_PSEUDO, EV_END = 1, 2, 3, 4, 5, 6
 CNT_LIFTS, CNT_FROZEN, CNT_WALLS, CNT_CHAINS, CNT_PSEUDO, CNT_NCOL = 0, 1, 2, 3, 4, 5
 
@@ -21,7 +22,7 @@ class Params(C.Structure):
     _fields_ = [("n", C.c_int64), ("sigma", C.c_double), ("eta", C.c_double),
                 ("ell", C.c_double), ("cells", C.c_int32), ("chains_per_cell", C.c_int32),
                 ("dir_mode", C.c_int32), ("start_mode", C.c_int32), ("seed", C.c_uint64),
-                ("system", C.c_uint32), ("pad", C.c_uint32)]
+                ("system", C.c_uint32), ("boundary", C.c_uint32)]
 
 
 class Event(C.Structure):
@@ -76,9 +77,9 @@ def _ptr(a, ct):
 
 
 def params(n, eta, ell, cells, dir_mode=DIR_ISO, seed=1, sigma=1.0, chains_per_cell=0,
-           start_mode=START_REPLACE, system=0):
+           start_mode=START_REPLACE, system=0, boundary=BOUNDARY_REFLECT):
     return Params(int(n), float(sigma), float(eta), float(ell), int(cells), int(chains_per_cell),
-                  int(dir_mode), int(start_mode), int(seed), int(system), 0)
+                  int(dir_mode), int(start_mode), int(seed), int(system), int(boundary))
 
 
 def box_length(n, sigma, eta):

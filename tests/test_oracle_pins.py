@@ -271,6 +271,87 @@ def test_walled_invariants():
         np.testing.assert_array_equal(st.x, st2.x)
 
 
+def test_rejection_undoes_every_chain_longer_than_the_cell():
+    """Rejection variant (Sec. 3.4): a straight chain's front advances by at
+    least ell along its direction, so with ell far above the cell's diagonal
+    every chain reaches a wall or a frozen disk and is undone: the
+    configuration and the contact sums stay exactly as they were."""
+    n, eta, C = 1024, 0.30, 4
+    p = O.params(n, eta, 100.0, C, seed=6, boundary=O.BOUNDARY_REJECT)
+    st = O.State(p)
+    x0, y0 = st.x.copy(), st.y.copy()
+    st.run(2)
+    np.testing.assert_array_equal(st.x, x0)
+    np.testing.assert_array_equal(st.y, y0)
+    cnt = st.acc_cnt.sum(axis=0)
+    assert cnt[O.CNT_LIFTS] == 0 and np.all(st.acc_delta == 0.0)
+    assert cnt[O.CNT_WALLS] + cnt[O.CNT_FROZEN] == cnt[O.CNT_CHAINS] == 2 * n
+
+
+def test_rejection_invariants():
+    """Rejection variant at a chain length that lets some chains finish:
+    every chain either ends with its full displacement or is rejected at a
+    wall or frozen disk and leaves its disks where they were; disks stay in
+    their cells; no overlaps; the counts add up."""
+    n, eta, C = 1024, 0.55, 4
+    p = O.params(n, eta, 1.0, C, seed=5, boundary=O.BOUNDARY_REJECT)
+    L = O.box_length(n, 1.0, eta)
+    w = L / C
+    st = O.State(p)
+    for sweep in range(3):
+        x0, y0 = st.x.copy(), st.y.copy()
+        cell_of = O.assign_cells(p, x0, y0, sweep)
+        sx, sy, _ = O.sweep_draws(p, sweep)
+        st2, ev = O.run_logged(p, x0, y0, sweep, 1)
+        cnt = st2.acc_cnt.sum(axis=0)
+        accepted = rejected = 0
+        for ch in np.unique(ev["chain"]):
+            e = ev[ev["chain"] == ch]
+            last = e["kind"][-1]
+            if last == O.EV_END:
+                accepted += 1
+                assert abs(e["s"].sum() - p.ell) < 1e-12 * len(e) + 1e-12
+                assert np.all(np.isin(e["kind"][:-1], [O.EV_LIFT]))
+            else:
+                rejected += 1
+                assert last in (O.EV_WALL_X, O.EV_WALL_Y, O.EV_FROZEN)
+                assert np.all(np.isin(e["kind"][:-1], [O.EV_LIFT]))
+        assert accepted > 0 and rejected > 0
+        assert accepted + rejected == cnt[O.CNT_CHAINS] == n
+        assert cnt[O.CNT_WALLS] + cnt[O.CNT_FROZEN] == rejected
+        assert cnt[O.CNT_LIFTS] <= (ev["kind"] == O.EV_LIFT).sum()
+        ux = (st2.x - sx) % L
+        uy = (st2.y - sy) % L
+        cx, cy = cell_of % C, cell_of // C
+        tol = 1e-9
+        inside_x = (ux >= cx * w - tol) & (ux <= (cx + 1) * w + tol) | ((cx == C - 1) & (ux < tol))
+        inside_y = (uy >= cy * w - tol) & (uy <= (cy + 1) * w + tol) | ((cy == C - 1) & (uy < tol))
+        assert inside_x.all() and inside_y.all()
+        assert _min_pair_distance(st2.x, st2.y, L) > 1.0 - 1e-12
+        st.run(1)
+        np.testing.assert_array_equal(st.x, st2.x)
+
+
+def test_rejected_chains_leave_no_trace():
+    """Rejection variant, one cell's phase replayed by hand: undoing a chain
+    restores the configuration bit for bit, so removing the rejected chains'
+    events from the log leaves, chain by chain, the moves of the accepted
+    ones; in particular a disk whose every chain was rejected keeps its bits."""
+    n, eta, C = 1024, 0.55, 4
+    p = O.params(n, eta, 1.5, C, seed=9, boundary=O.BOUNDARY_REJECT)
+    st = O.State(p)
+    x0, y0 = st.x.copy(), st.y.copy()
+    st2, ev = O.run_logged(p, x0, y0, 0, 1)
+    moved_by_accepted = set()
+    for ch in np.unique(ev["chain"]):
+        e = ev[ev["chain"] == ch]
+        if e["kind"][-1] == O.EV_END:
+            moved_by_accepted.update(int(a) for a in e["active"])
+    untouched = np.setdiff1d(np.arange(n), np.array(sorted(moved_by_accepted), dtype=np.int64))
+    np.testing.assert_array_equal(st2.x[untouched], x0[untouched])
+    np.testing.assert_array_equal(st2.y[untouched], y0[untouched])
+
+
 def test_frozen_reflection_is_specular():
     """After a contact with a frozen disk the direction is mirrored about the
     contact normal: angle of incidence equals angle of reflection."""
