@@ -90,6 +90,16 @@ typedef enum {
  * Setting both bits is EC_E_INVALID; the systems of a batch share them. */
 #define EC_FLAG_PHASE_LAUNCHES 2u
 #define EC_FLAG_ONE_LAUNCH 4u
+/* Rejection at the cell boundary (walled cells, FP64): a chain that would
+ * take a centre across its cell's wall or hit a frozen disk is rejected and
+ * every move it made is undone -- the variant Sec. 3.4 attributes to the
+ * striped decomposition, instead of the paper's reflection.  Tallies: lifts
+ * and the contact sum of accepted chains only; the wall and frozen counts
+ * are the rejections they caused; chains counts all.  The EC pressure
+ * estimator does not apply (use the pair-correlation route).  A chain may
+ * make at most 256 lifts (device error bit 32 beyond).  The systems of a
+ * batch share it. */
+#define EC_FLAG_REJECT 8u
 
 typedef struct {
   uint32_t abi_version;     /* must equal EC_ABI_VERSION                                    */

@@ -87,6 +87,10 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
   if (p->abi_version != EC_ABI_VERSION) { *why = "abi_version mismatch"; return EC_E_INVALID; }
   if (p->n_disks < 1 || p->n_disks > 0x7FFFFFF0LL) { *why = "n_disks out of range"; return EC_E_INVALID; }
   if (!(p->sigma > 0.0) || !std::isfinite(p->sigma)) { *why = "sigma must be > 0"; return EC_E_INVALID; }
+  if ((p->flags & EC_FLAG_REJECT) &&
+      (p->cells_per_side == 1 || p->precision != EC_PREC_FP64)) {
+    *why = "EC_FLAG_REJECT needs walled cells and FP64"; return EC_E_UNSUPPORTED;
+  }
   if ((p->flags & EC_FLAG_PHASE_LAUNCHES) && (p->flags & EC_FLAG_ONE_LAUNCH)) {
     *why = "EC_FLAG_PHASE_LAUNCHES and EC_FLAG_ONE_LAUNCH exclude each other"; return EC_E_INVALID;
   }
@@ -122,7 +126,8 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
     out->nb = nb;
     out->cap_own = own_capacity(w, p->sigma);
     out->lds_per_cell =
-        ec::cell_lds_layout(nb + 2, out->cap_own, p->precision == EC_PREC_FP32_SCREEN).bytes;
+        ec::cell_lds_layout(nb + 2, out->cap_own, p->precision == EC_PREC_FP32_SCREEN,
+                            (p->flags & EC_FLAG_REJECT) != 0).bytes;
     // Default: four cells (four waves) per workgroup when their LDS fits one CU.
     // The waves of one workgroup go to the four SIMDs of one CU; one-wave
     // workgroups leave the SIMD choice to the dispatcher, which has been
@@ -244,6 +249,7 @@ ec::LaunchShape shape_of(const ec::Dev& d, const ec_params& p) {
   sh.cpb = d.cells_per_block;
   sh.max_lds_per_cell = d.lds_per_cell;
   sh.one_launch = d.C > 1 && !(p.flags & EC_FLAG_PHASE_LAUNCHES);  // a system swept alone
+  sh.reject = d.reject != 0;
   return sh;
 }
 
@@ -319,6 +325,7 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   d.psi_nb = (int32_t*)(b + lay.psi_nb);
   d.psi_err = (unsigned long long*)(b + lay.psi_err);
   d.dep_wait_ticks = kDefaultDepWaitTicks;
+  d.reject = (p->flags & EC_FLAG_REJECT) ? 1 : 0;
   d.search = (p->flags & EC_FLAG_SCAN_SEARCH) ? 1 : 0;
   d.n = p->n_disks;
   d.sigma = p->sigma;
@@ -457,7 +464,8 @@ static ec_status check_err(ec_system s) {
     char buf[512];
     std::snprintf(buf, sizeof buf,
                   "device check failed (bits 0x%x: 1 cell capacity, 2 bin capacity, 4 events per "
-                  "chain, 8 draw retries, 16 dependency wait); first tripped chain: cell %.0f "
+                  "chain, 8 draw retries, 16 dependency wait, 32 undo log); first tripped chain: "
+                  "cell %.0f "
                   "chain %.0f sweep %.0f "
                   "phase %.0f pos (%.17g, %.17g) dir (%.17g, %.17g) rem %.17g slot %.0f id %.0f "
                   "n_own %.0f",
@@ -817,7 +825,7 @@ ec_status batch_layout(const ec_params* ps, int32_t n, BatchLayout* bl, std::vec
     if (ps[i].precision != ps[0].precision) {
       *why = "the systems of a batch share one precision"; return EC_E_UNSUPPORTED;
     }
-    if ((ps[i].flags ^ ps[0].flags) & (EC_FLAG_PHASE_LAUNCHES | EC_FLAG_ONE_LAUNCH)) {
+    if ((ps[i].flags ^ ps[0].flags) & (EC_FLAG_PHASE_LAUNCHES | EC_FLAG_ONE_LAUNCH | EC_FLAG_REJECT)) {
       *why = "the systems of a batch share one schedule"; return EC_E_UNSUPPORTED;
     }
     bl->off[(size_t)i] = o;
@@ -930,6 +938,7 @@ ec_status ec_init_batch(const ec_params* ps, int32_t n_sys, void* ws, size_t ws_
   sh.periodic = false;
   sh.fp32_screen = ps[0].precision == EC_PREC_FP32_SCREEN;
   sh.one_launch = (ps[0].flags & EC_FLAG_ONE_LAUNCH) != 0;  // phase launches unless asked
+  sh.reject = (ps[0].flags & EC_FLAG_REJECT) != 0;
   sh.cpb = 1;
   for (int32_t i = 0; i < n_sys; ++i) {
     ec_params p = ps[i];

@@ -22,7 +22,8 @@ enum {
   ERR_BIN_CAP = 2,     // more than four centres in one LDS bin
   ERR_EVENT_CAP = 4,   // a chain exceeded kMaxEventsPerChain events
   ERR_DRAW_CAP = 8,    // a rejection draw exceeded kMaxDrawTries attempts
-  ERR_DEP_WAIT = 16    // a cell waited longer than dep_wait_ticks for a neighbour of an earlier phase
+  ERR_DEP_WAIT = 16,   // a cell waited longer than dep_wait_ticks for a neighbour of an earlier phase
+  ERR_UNDO_CAP = 32    // rejection variant: a chain made more lifts than the undo log holds
 };
 
 // Events allowed in one chain before the sweep gives up with ERR_EVENT_CAP.
@@ -44,6 +45,8 @@ constexpr int kMaxGrBins = 1024;
 // Events hashed together, one per lane, by the walled-cell kernel's digest
 // (event ids then fit in 29 bits: N < 2^29 - 3).
 constexpr int kDigestBatch = 64;
+// Rejection variant: lifts of one chain that can be undone (LDS log entries).
+constexpr int kUndoCap = 256;
 
 // Everything a kernel needs: device pointers into the caller's workspace and
 // the derived constants.  Passed by value.
@@ -86,6 +89,7 @@ struct Dev {
   int32_t lds_per_cell, cells_per_block;
   int32_t search;                   // 0: 4x4-bin window with guard; 1: scan of every slot
   int64_t dep_wait_ticks;           // one-launch sweep: limit of one wait, 100 MHz clock ticks
+  int32_t reject;                   // 1: a chain reaching a wall or a frozen disk is undone
   uint64_t seed;
   uint32_t system;
 };
@@ -95,11 +99,13 @@ struct Dev {
 // then the own-disk tables and one sink slot per lane (a target for the
 // lanes that do not store when one lane writes a position).
 struct CellLds {
-  int32_t off_pos, off_meta, off_mask, off_own_gid, off_own_loc, off_tmp, off_sink, off_pos32, bytes;
+  int32_t off_pos, off_meta, off_mask, off_own_gid, off_own_loc, off_tmp, off_sink, off_pos32, off_undo,
+      bytes;
 };
 
 // fp32: also an FP32 copy of every slot's position (the screened form).
-__host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own, bool fp32) {
+// reject: an undo log of kUndoCap entries (slots and old position, 32 B each).
+__host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own, bool fp32, bool reject) {
   CellLds l;
   int slots = gridb * gridb * 4;
   int o = 0;
@@ -112,6 +118,8 @@ __host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own, bool 
   o = (o + 15) & ~15;
   l.off_sink = o;     o += 16 * 64;
   l.off_pos32 = o;    o += fp32 ? 8 * slots : 0;
+  o = (o + 15) & ~15;
+  l.off_undo = o;     o += reject ? 32 * kUndoCap : 0;
   l.bytes = (o + 15) & ~15;
   return l;
 }
@@ -127,6 +135,7 @@ struct LaunchShape {
   bool any_distinct;        // some system uses the distinct-start control
   bool fp32_screen;         // the FP32-screened phase kernel (same for all)
   bool one_launch;          // all four phases in one launch (k_sweep_cells), else one per phase
+  bool reject;              // rejection at the cell boundary (same for all)
   int64_t max_n;            // disks
   int64_t max_chains;       // chains per sweep
   int32_t max_cells;        // C * C

@@ -528,8 +528,10 @@ __device__ __forceinline__ int32_t load_err(const Dev& d) {
 // One active cell of colour phase q (Sec. 3.4, steps 3-6): stage the own
 // disks and the frozen band into LDS, run the cell's chains, write back.  One
 // wavefront; base is its LDS region.  Returns early, with d.err set, when a
-// capacity check fails.
-template <int PREC>
+// capacity check fails.  REJ 1: a chain that reaches a wall or a frozen disk
+// is rejected and undone (the rejection variant of Sec. 3.4); every event then
+// takes the general path, which logs each lift for the undo.
+template <int PREC, int REJ>
 __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, const SweepDraws& dr,
                                            const int q, const int blk, unsigned char* const base,
                                            const int lane) {
@@ -543,7 +545,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
   const int gridb = d.gridb, nb = d.nb;
   const int nslots = gridb * gridb * 4;
 
-  const CellLds lay = cell_lds_layout(gridb, d.cap_own, PREC == 1);
+  const CellLds lay = cell_lds_layout(gridb, d.cap_own, PREC == 1, REJ == 1);
   double2* pos = (double2*)(base + lay.off_pos);
   uint64_t* meta = (uint64_t*)(base + lay.off_meta);
   int32_t* mask = (int32_t*)(base + lay.off_mask);
@@ -554,6 +556,9 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
   // moved disk, so the store needs no change of the execution mask
   double2* const sink = (double2*)(base + lay.off_sink) + lane;
   float2* pos32 = (float2*)(base + lay.off_pos32);  // PREC 1 only
+  // REJ 1 only: per logged lift the old position, then (slot before, slot after)
+  double2* undo_pos = (double2*)(base + lay.off_undo);
+  int2* undo_slot = (int2*)(undo_pos + kUndoCap);
   float2* const sink32 = (float2*)sink;
 
   // ---- stage: own disks, sorted by id -----------------------------------
@@ -707,6 +712,10 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     double ax = ap.x, ay = ap.y;
     double rem = d.ell;
     int n_events = 0;
+    // REJ 1: the chain's undo log, contact sum and lifts (counted once accepted)
+    int n_undo = 0;
+    double chain_acc = 0.0;
+    uint32_t chain_lifts = 0;
     int wx0, wy0, wbase;
     EC_WINDOW(abx, aby, xneg, yneg);
     double2 p = pos[wbase + loff];
@@ -788,7 +797,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       // staying in its bin and chain length left over
       constexpr int kFastMask = (7 << 16) | (1 << 20) | (1 << 21) | (1 << 22);
       constexpr int kFast = (EV_LIFT << 16) | (1 << 21);
-      if ((packed & kFastMask) == kFast) {
+      if (REJ == 0 && (packed & kFastMask) == kFast) {
         {
           const uint64_t sb = (uint64_t)__double_as_longlong(step);
           const uint32_t tag = ((uint32_t)EV_LIFT << 29) | (wgid & ~kFrozenBit);
@@ -861,6 +870,9 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       const int kind = (packed >> 16) & 7;
       const bool ends = ((packed >> 20) & 1) != 0;
       const int nbx = packed & 0xFF, nby = (packed >> 8) & 0xFF;
+      // REJ 1: a wall or a frozen disk rejects the chain
+      const bool rejected = REJ == 1 && !ends && kind != EV_LIFT;
+      const double pax = ax, pay = ay;  // position before this event's move
       ax = nax;
       ay = nay;
       // event record for the digest: bits of the step, kind << 32 | id
@@ -878,6 +890,40 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         rec_hi = mine ? (uint32_t)(sb >> 32) : rec_hi;
         rec_tag = mine ? tag : rec_tag;
       }
+      if (REJ == 1 && !rejected && !ends) {
+        // log the lift's move: slot before it and old position (the slot after
+        // it is known below); a full log stops the sweep with an error
+        if (n_undo == kUndoCap) {
+          if (lane == 0) atomicOr(d.err, ERR_UNDO_CAP);
+          stop = 1;
+        } else if (lane == 0) {
+          undo_pos[n_undo] = make_double2(pax, pay);
+          undo_slot[n_undo] = make_int2(a_loc, a_loc);
+        }
+      }
+      if (rejected) {
+        // undo every logged lift, latest first: each disk goes back to the
+        // slot it left (a slot vacated in between was refilled only by moves
+        // that are undone before it) and to its old position
+        if (lane == 0) {
+          for (int u = n_undo - 1; u >= 0; --u) {
+            const int2 sl = undo_slot[u];
+            const double2 old = undo_pos[u];
+            if (sl.y != sl.x) {
+              const uint64_t mv = meta[sl.y];
+              mask[sl.y >> 2] = mask[sl.y >> 2] & ~(1 << (sl.y & 3));
+              pos[sl.y] = nan2;
+              mask[sl.x >> 2] = mask[sl.x >> 2] | (1 << (sl.x & 3));
+              meta[sl.x] = mv;
+              own_loc[(int)(uint32_t)(mv >> 32)] = sl.x;
+            }
+            pos[sl.x] = old;
+          }
+        }
+        n_undo = 0;
+        if (kind == EV_FROZEN) n_frozen += 1;
+        else n_wall += 1;
+      } else
       // store the moved disk; move it to another bin if it crossed a bin edge
       if (nbx == abx && nby == aby) {
         double2* const dst = (lane == 0) ? pos + a_loc : sink;
@@ -915,16 +961,27 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
           aby = nby;
         }
       }
+      if (REJ == 1 && !rejected && !ends && stop == 0) {
+        if (lane == 0) undo_slot[n_undo].y = a_loc;  // the slot the disk now holds
+        n_undo += 1;
+      }
       __builtin_amdgcn_wave_barrier();
       if (++n_ring == kDigestBatch) {
         h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first);
         ring_first += kDigestBatch;
         n_ring = 0;
       }
-      if (!ends && kind == EV_LIFT) {
+      if (rejected) {
+        ended = 1;
+      } else if (!ends && kind == EV_LIFT) {
         // straight chain: the hit disk goes on in the same direction
-        acc = acc + fma(wpx - ax, dx, (wpy - ay) * dy);
-        n_lift += 1;
+        if (REJ == 1) {
+          chain_acc = chain_acc + fma(wpx - ax, dx, (wpy - ay) * dy);
+          chain_lifts += 1;
+        } else {
+          acc = acc + fma(wpx - ax, dx, (wpy - ay) * dy);
+          n_lift += 1;
+        }
         rem = rem - e;
         a_loc = w_slot;
         a_gid = wgid;
@@ -935,6 +992,10 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         ay = wpy;
       } else if (ends) {
         ended = 1;
+        if (REJ == 1) {  // accepted: its contact sum and lifts count
+          acc = acc + chain_acc;
+          n_lift += chain_lifts;
+        }
       } else {
         rem = rem - e;
         if (kind == EV_FROZEN) {
@@ -1018,7 +1079,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
 
 // Colour phase q of a sweep: one launch per phase, one wavefront per active
 // cell; the launch boundary separates the phases.
-template <int PREC>
+template <int PREC, int REJ>
 __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q) {
   const Dev d = ds[blockIdx.y];
   const int64_t sweep = *d.sweep_ctr;
@@ -1029,7 +1090,7 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
   const int blk = blockIdx.x * d.cells_per_block + wave;
   if (blk >= half * half) return;  // the whole wave leaves; no workgroup barrier follows
   const SweepDraws dr = *d.draws;
-  phase_cell<PREC>(d, sweep, dr, q, blk, lds_raw + (size_t)wave * d.lds_per_cell, lane);
+  phase_cell<PREC, REJ>(d, sweep, dr, q, blk, lds_raw + (size_t)wave * d.lds_per_cell, lane);
 }
 
 // All four colour phases of a sweep in one launch.  The phases order only
@@ -1049,7 +1110,7 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
 // ends.  Every wait is also bounded by d.dep_wait_ticks (100 MHz clock) and
 // abandoned when any wave has set d.err: on either, the wave sets or sees the
 // error and leaves, and the sweep reports it.
-template <int PREC>
+template <int PREC, int REJ>
 __global__ void __launch_bounds__(256) k_sweep_cells(const Dev* __restrict__ ds) {
   const Dev d = ds[blockIdx.y];
   const int64_t sweep = *d.sweep_ctr;
@@ -1110,7 +1171,7 @@ __global__ void __launch_bounds__(256) k_sweep_cells(const Dev* __restrict__ ds)
       // the neighbours' write-backs are visible to the staging loads below
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    phase_cell<PREC>(d, sweep, dr, q, blk, base, lane);
+    phase_cell<PREC, REJ>(d, sweep, dr, q, blk, base, lane);
     // this cell's write-back before its flag
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (lane == 0)
@@ -1281,8 +1342,9 @@ hipError_t launch_zero_tallies(const Dev* ds, int32_t n_cells, hipStream_t st) {
 }
 
 hipError_t set_phase_lds_limit(int bytes) {
-  const void* fns[4] = {(const void*)k_phase<0>, (const void*)k_phase<1>, (const void*)k_sweep_cells<0>,
-                        (const void*)k_sweep_cells<1>};
+  const void* fns[6] = {(const void*)k_phase<0, 0>,       (const void*)k_phase<1, 0>,
+                        (const void*)k_phase<0, 1>,       (const void*)k_sweep_cells<0, 0>,
+                        (const void*)k_sweep_cells<1, 0>, (const void*)k_sweep_cells<0, 1>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -1323,9 +1385,11 @@ hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
     // as many wavefronts as one phase has cells; each takes cells of all phases
     if (ev) (void)hipEventRecord(ev->begin[0], st);
     if (sh.fp32_screen)
-      hipLaunchKernelGGL(k_sweep_cells<1>, dim3(grid, ns), dim3(64 * cpb), lds, st, ds);
+      hipLaunchKernelGGL((k_sweep_cells<1, 0>), dim3(grid, ns), dim3(64 * cpb), lds, st, ds);
+    else if (sh.reject)
+      hipLaunchKernelGGL((k_sweep_cells<0, 1>), dim3(grid, ns), dim3(64 * cpb), lds, st, ds);
     else
-      hipLaunchKernelGGL(k_sweep_cells<0>, dim3(grid, ns), dim3(64 * cpb), lds, st, ds);
+      hipLaunchKernelGGL((k_sweep_cells<0, 0>), dim3(grid, ns), dim3(64 * cpb), lds, st, ds);
     if (ev) (void)hipEventRecord(ev->end[0], st);
     hipLaunchKernelGGL(k_sweep_done, dim3(1, ns), dim3(64), 0, st, ds);
     return hipGetLastError();
@@ -1333,9 +1397,11 @@ hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
   for (int q = 0; q < 4; ++q) {
     if (ev) (void)hipEventRecord(ev->begin[q], st);
     if (sh.fp32_screen)
-      hipLaunchKernelGGL(k_phase<1>, dim3(grid, ns), dim3(64 * cpb), lds, st, ds, q);
+      hipLaunchKernelGGL((k_phase<1, 0>), dim3(grid, ns), dim3(64 * cpb), lds, st, ds, q);
+    else if (sh.reject)
+      hipLaunchKernelGGL((k_phase<0, 1>), dim3(grid, ns), dim3(64 * cpb), lds, st, ds, q);
     else
-      hipLaunchKernelGGL(k_phase<0>, dim3(grid, ns), dim3(64 * cpb), lds, st, ds, q);
+      hipLaunchKernelGGL((k_phase<0, 0>), dim3(grid, ns), dim3(64 * cpb), lds, st, ds, q);
     if (ev) (void)hipEventRecord(ev->end[q], st);
   }
   hipLaunchKernelGGL(k_sweep_done, dim3(1, ns), dim3(64), 0, st, ds);

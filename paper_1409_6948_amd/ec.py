@@ -19,6 +19,7 @@ EC_START_REPLACE, EC_START_DISTINCT = 0, 1
 EC_FLAG_SCAN_SEARCH = 1
 EC_FLAG_PHASE_LAUNCHES = 2
 EC_FLAG_ONE_LAUNCH = 4
+EC_FLAG_REJECT = 8
 EC_ABI_VERSION = 1
 COUNT_NAMES = ("lifts", "frozen", "walls", "chains", "pseudo")
 

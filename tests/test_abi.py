@@ -61,6 +61,8 @@ def test_workspace_sizes_scale_with_n():
     (dict(cells=1, n=4096), E.EC_E_UNSUPPORTED),       # one periodic cell holds <= 2048 disks
     (dict(cells_per_block=3), E.EC_E_INVALID),
     (dict(flags=E.EC_FLAG_PHASE_LAUNCHES | E.EC_FLAG_ONE_LAUNCH), E.EC_E_INVALID),
+    (dict(flags=E.EC_FLAG_REJECT, cells=1, n=1024), E.EC_E_UNSUPPORTED),   # walled cells only
+    (dict(flags=E.EC_FLAG_REJECT, precision=E.EC_PREC_FP32_SCREEN), E.EC_E_UNSUPPORTED),
 ])
 def test_invalid_parameters_rejected(kw, status):
     with pytest.raises(E.ECError) as ei:

@@ -114,6 +114,23 @@ def test_batch_one_launch_equals_solo_runs(P):
     b.close()
 
 
+def test_batch_rejection_variant_equals_solo_runs(P):
+    """Rejection at the cell boundary (ell = 3 sigma) in a batch follows the
+    solo trajectories."""
+    cfgs = inputs.batch_systems(64, seed=0)[:12]
+    ps = [P.make_params(c["n"], c["eta"], 3.0, c["cells"], dir_mode=c["dir_mode"], seed=c["seed"],
+                        system=i, flags=P.EC_FLAG_REJECT) for i, c in enumerate(cfgs)]
+    sweeps = 2
+    _say("[batch] rejection variant against solo runs")
+    solos = _solo_states(P, ps, sweeps)
+    b = P.Batch(ps)
+    b.set_graph(True)
+    b.sweep(sweeps)
+    b.stream.synchronize()
+    _assert_same(b, solos, sweeps)
+    b.close()
+
+
 def test_autotune_leaves_the_state_untouched(P):
     cfgs = inputs.batch_systems(64, seed=0)[:12]
     ps = _params(P, cfgs)

@@ -43,9 +43,9 @@ def _gpu_system(P, n, eta, ell, cells, dir_mode, seed=1, chains_per_cell=0, star
 
 
 def _oracle_state(n, eta, ell, cells, dir_mode, seed=1, chains_per_cell=0, start_mode=0, x=None,
-                  y=None):
+                  y=None, boundary=0):
     p = O.params(n, eta, ell, cells, dir_mode=dir_mode, seed=seed,
-                 chains_per_cell=chains_per_cell, start_mode=start_mode)
+                 chains_per_cell=chains_per_cell, start_mode=start_mode, boundary=boundary)
     return O.State(p, x, y)
 
 
@@ -54,7 +54,8 @@ def _compare_full(P, n, eta, ell, cells, dir_mode, sweeps, seed=1, chains_per_ce
     _say(f"[parity] n={n} eta={eta} ell={ell} C={cells} dir={dir_mode} sweeps={sweeps} "
          f"seed={seed} n_m={chains_per_cell} start={start_mode} cpb={cells_per_block} "
          f"flags={flags} precision={precision}")
-    st = _oracle_state(n, eta, ell, cells, dir_mode, seed, chains_per_cell, start_mode, x, y)
+    boundary = 1 if flags & P.EC_FLAG_REJECT else 0
+    st = _oracle_state(n, eta, ell, cells, dir_mode, seed, chains_per_cell, start_mode, x, y, boundary)
     g = _gpu_system(P, n, eta, ell, cells, dir_mode, seed, chains_per_cell, start_mode,
                     cells_per_block, flags, precision)
     gx, gy = g.get_positions()
@@ -169,6 +170,31 @@ def test_dependency_wait_limit(P):
     h.set_dep_wait_limit(0.0)
     h.sweep(1)
     h.get_positions()
+
+
+@pytest.mark.parametrize("n,eta,cells,ell,sweeps,flags", [
+    (1024, 0.55, 4, 1.0, 3, 0),
+    (4096, 0.70, 8, 2.0, 3, 0),
+    (4096, 0.30, 8, 3.0, 2, 0),           # dilute: long flights, full-cell searches
+    (2304, 0.65, 6, 2.0, 2, 2),           # one launch per phase
+    (1024, 0.30, 4, 100.0, 2, 0),         # every chain longer than the cell: all undone
+])
+def test_rejection_variant(P, n, eta, cells, ell, sweeps, flags):
+    """Rejection at the cell boundary against the oracle bit for bit."""
+    _compare_full(P, n, eta, ell, cells, 1, sweeps, seed=5, flags=flags | P.EC_FLAG_REJECT)
+
+
+def test_rejection_identity_and_counts(P):
+    """ell far above the cell: every chain is rejected and the configuration
+    keeps its bits; the wall and frozen counts are the rejections."""
+    g = _gpu_system(P, 1024, 0.30, 100.0, 4, 1, seed=6, flags=P.EC_FLAG_REJECT)
+    x0, y0 = g.get_positions()
+    g.sweep(2)
+    x1, y1 = g.get_positions()
+    np.testing.assert_array_equal(x0, x1)
+    np.testing.assert_array_equal(y0, y1)
+    _, _, c = g.measure_pressure()
+    assert c["lifts"] == 0 and c["walls"] + c["frozen"] == c["chains"] == 2048
 
 
 def test_fixed_chains_per_cell(P):
