@@ -17,6 +17,9 @@ With --workload nm-scan it compares the pressure against n_m for both start
 rules (Fig. 3 right); --workload serial-ref compares PEC with serial EC of
 the same N.
 
+With --workload boundary-rules it compares reflection with rejection at the
+cell boundary, each with both start rules (Fig. 3).
+
 With --workload psi6-delaunay it times the Delaunay-neighbour Psi at N = 1M;
 with --workload tau it reports the autocorrelation time (eq. tau) of 8
 seeded liquid systems from a Psi series.
@@ -134,6 +137,8 @@ def main():
         return bench_batch(args, torch, P)
     if args.workload == "start-rules":
         return bench_start_rules(args, torch, P)
+    if args.workload == "boundary-rules":
+        return bench_boundary_rules(args, torch, P)
     if args.workload == "serial-ref":
         return bench_serial_ref(args, torch, P)
     if args.workload == "nm-scan":
@@ -545,6 +550,74 @@ def bench_nm_scan(args, torch, P):
     line = {"workload": "nm-scan", "n_disks": n, "eta": eta, "cells_per_side": C, "ell": ell,
             "seeds": seeds, "warmup_sweeps_at_n_m_64": warm, "sweeps_at_n_m_64": meas,
             "cases": out, "seconds": time.perf_counter() - t0}
+    print(json.dumps(line), flush=True)
+
+def bench_boundary_rules(args, torch, P):
+    """Reflection (the paper's rule) against rejection at the cell boundary
+    (Sec. 3.4), each with starts drawn with replacement and with shuffled
+    distinct starts (Fig. 3 left and right): N = 16384, eta = 0.70, 16 x 16
+    cells, ell = 0.2 sigma (the front of a straight chain advances by about
+    sigma per lift, some 10 ell here, and rejection needs it to stay inside
+    the cell), n_m = n_c, 8 seeds per case, g(r) sampled every 10 sweeps;
+    pressure from g(r) at contact (the EC estimator does not apply to
+    rejected chains) and, for reflection, from the lift tallies."""
+    import math
+    n, eta, ell, C, seeds = 16384, 0.70, 0.2, 16, 8
+    box = math.sqrt(n * math.pi / (4.0 * eta))
+    warm, meas = max(args.warmup, 1) * 300, max(args.steps, 1) * 15
+
+    def stats(v):
+        m = sum(v) / len(v)
+        return m, math.sqrt(sum((x - m) ** 2 for x in v) / (len(v) - 1) / len(v))
+
+    t0 = time.perf_counter()
+    res = {}
+    for bname, bflag in (("reflect", 0), ("reject", P.EC_FLAG_REJECT)):
+        ps = []
+        for rule in (P.EC_START_REPLACE, P.EC_START_DISTINCT):
+            for sd in range(seeds):
+                ps.append(P.make_params(n, eta, ell, C, seed=sd + 1, start_mode=rule, system=len(ps),
+                                        flags=bflag))
+        b = P.Batch(ps)
+        b.set_graph(True)
+        b.sweep(warm)
+        b.stream.synchronize()
+        for sy in b.systems:
+            sy.reset_tallies()
+            sy.gr_reset()
+        for _ in range(meas):
+            b.sweep(10)
+            for sy in b.systems:
+                sy.gr_accumulate(1.5, 100)
+        b.stream.synchronize()
+        zs = [_z_routes(P, sy, n, box) for sy in b.systems]
+        counts = [sy.measure_pressure()[2] for sy in b.systems]
+        b.close()
+        for r, rule in enumerate(("replacement", "distinct")):
+            part = zs[r * seeds:(r + 1) * seeds]
+            cnt = counts[r * seeds:(r + 1) * seeds]
+            chains = sum(c["chains"] for c in cnt)
+            rejected = sum(c["walls"] + c["frozen"] for c in cnt) if bflag else 0
+            res[(bname, rule)] = {"gr_contact": stats([z[1] for z in part]),
+                                  "ec": stats([z[0] for z in part]) if not bflag else None,
+                                  "rejected_fraction": rejected / chains if chains else None}
+        print(f"# boundary-rules: {bname} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+              flush=True)
+    ref = res[("reflect", "replacement")]["gr_contact"]
+    cases = []
+    for (bname, rule), v in res.items():
+        m, se = v["gr_contact"]
+        c = {"boundary": bname, "rule": rule, "rejected_fraction": v["rejected_fraction"],
+             "gr_contact": {"z_mean": m, "z_stderr": se,
+                            "minus_reflect_replacement_in_stderr":
+                                (m - ref[0]) / math.hypot(se, ref[1]) if (bname, rule) != ("reflect", "replacement") else None}}
+        if v["ec"] is not None:
+            c["ec"] = {"z_mean": v["ec"][0], "z_stderr": v["ec"][1]}
+        cases.append(c)
+    line = {"workload": "boundary-rules", "n_disks": n, "eta": eta, "cells_per_side": C, "ell": ell,
+            "seeds": seeds, "warmup_sweeps": warm, "sweeps": meas * 10, "gr_samples": meas,
+            "cases": cases,
+            "seconds": time.perf_counter() - t0}
     print(json.dumps(line), flush=True)
 
 if __name__ == "__main__":

@@ -76,3 +76,47 @@ def test_distinct_starts_bias_the_pressure(P):
     # the shuffled rule: the contact pressure lies far from the correct one
     assert gr_r[0] - gr_d[0] > 5.0 * math.hypot(gr_r[1], gr_d[1])
     assert ec_r[0] - ec_d[0] > 4.0 * math.hypot(ec_r[1], ec_d[1])
+
+
+def test_rejection_at_the_boundary_samples_the_same_pressure(P):
+    """Rejection at the cell boundary (Sec. 3.4) with starts drawn with
+    replacement gives the contact pressure of the paper's reflection; with
+    shuffled distinct starts both boundary rules are far off (Fig. 3).
+    N = 16384, eta = 0.70, 16 x 16 cells, ell = 0.2 sigma, 8 seeds per case,
+    1500 + 1500 sweeps, g(r) every 10 sweeps."""
+    box = math.sqrt(N * math.pi / (4.0 * ETA))
+    z = {}
+    for bname, bflag in (("reflect", 0), ("reject", P.EC_FLAG_REJECT)):
+        ps = []
+        for rule in (P.EC_START_REPLACE, P.EC_START_DISTINCT):
+            for seed in range(1, SEEDS + 1):
+                ps.append(P.make_params(N, ETA, 0.2, CELLS, seed=seed, start_mode=rule, system=len(ps),
+                                        flags=bflag))
+        _say(f"[boundary-rules] {bname}: {len(ps)} systems")
+        b = P.Batch(ps)
+        try:
+            b.set_graph(True)
+            b.sweep(1500)
+            for s in b.systems:
+                s.gr_reset()
+            for _ in range(150):
+                b.sweep(10)
+                for s in b.systems:
+                    s.gr_accumulate(R_MAX, BINS)
+            zs = []
+            for s in b.systems:
+                counts, samples, ov = s.gr_counts()
+                assert ov == 0
+                zs.append(P.gr_normalize(N, box, 1.0, R_MAX, counts, samples, FIT)[3])
+        finally:
+            b.close()
+        z[(bname, "replacement")] = _mean_se(zs[:SEEDS])
+        z[(bname, "distinct")] = _mean_se(zs[SEEDS:])
+    for k, v in z.items():
+        _say(f"[boundary-rules] {k}: Z(g) {v[0]:.4f} +- {v[1]:.4f}")
+    ref = z[("reflect", "replacement")]
+    rej = z[("reject", "replacement")]
+    assert abs(rej[0] - ref[0]) < 3.0 * math.hypot(rej[1], ref[1])
+    for bname in ("reflect", "reject"):
+        dist = z[(bname, "distinct")]
+        assert ref[0] - dist[0] > 10.0 * math.hypot(ref[1], dist[1])
