@@ -127,7 +127,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
-              f"decomposition is a design note, not part of this build", file=sys.stderr)
+              f"decomposition is described, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

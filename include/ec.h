@@ -53,8 +53,8 @@ typedef enum {
   EC_E_OVERLAP = 2,     /* positions given with two disks closer than sigma  */
   EC_E_HIP = 3,         /* a HIP runtime call failed (see ec_last_error)     */
   EC_E_NOMEM = 4,       /* workspace too small                               */
-  EC_E_STATE = 5,       /* a device-side capacity check failed in a sweep    */
-  EC_E_UNSUPPORTED = 6  /* valid request this build does not implement       */
+  EC_E_STATE = 5,       /* a device check failed in a sweep, or wrong handle */
+  EC_E_UNSUPPORTED = 6  /* valid request that is not implemented             */
 } ec_status;
 
 typedef enum {
