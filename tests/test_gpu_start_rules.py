@@ -1,4 +1,8 @@
-"""Negative control of the start rule (Sec. 3.4, Fig. 2 and 3): with n_m > 1
+"""Statistical checks on the device with fixed seeds: the start rules and the
+boundary rules against each other (Sec. 3.4, Fig. 3), and the mean free path
+the paper prints.
+
+Negative control of the start rule (Sec. 3.4, Fig. 2 and 3): with n_m > 1
 chains per cell, start disks drawn with replacement give one pressure by
 both routes (lift tallies, eq. EC pressure; g(r) at contact, eq. pressure),
 while a shuffled list of distinct start disks gives a pressure that differs
@@ -120,3 +124,20 @@ def test_rejection_at_the_boundary_samples_the_same_pressure(P):
     for bname in ("reflect", "reject"):
         dist = z[(bname, "distinct")]
         assert ref[0] - dist[0] > 10.0 * math.hypot(ref[1], dist[1])
+
+
+def test_mean_free_path_at_eta_071_matches_the_paper(P):
+    """The mean free path the paper prints for eta = 0.71 (tests/golden/
+    mean_free_path.json), on the device: N = 65536, 16 x 16 cells,
+    ell = 20 sigma, sweeps 6-15 from the lattice."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mean_free_path.json")))
+    g = P.System(P.make_params(65536, gold["eta"], 20.0, 16, seed=4))
+    g.sweep(5)
+    g.reset_tallies()
+    g.sweep(10)
+    _, _, c = g.measure_pressure()
+    lam = 20.0 * c["chains"] / (c["lifts"] + c["frozen"])
+    _say(f"[mean-free-path] eta {gold['eta']}: lambda = {lam:.4f} sigma")
+    assert abs(lam - gold["lambda0_over_sigma"]) <= 0.005

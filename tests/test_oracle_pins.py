@@ -785,3 +785,21 @@ def test_delaunay_planar_patch_equals_periodic():
         a = sorted(map(tuple, np.round(got, 9)))
         b = sorted(map(tuple, np.round(offsets[k], 9)))
         assert a == b
+
+
+def test_mean_free_path_at_eta_071_matches_the_paper():
+    """The paper prints the mean free path at eta = 0.71 (tests/golden/
+    mean_free_path.json).  Measured as ell / (disk contacts per chain) over
+    sweeps 3-4 of a 4096-disk system (4 x 4 cells, ell = 20 sigma) from the
+    lattice: within the printed precision."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mean_free_path.json")))
+    p = O.params(4096, gold["eta"], 20.0, 4, seed=2)
+    st = O.State(p)
+    st.run(2)
+    c0 = st.acc_cnt.sum(axis=0).astype(float)
+    st.run(2)
+    d = st.acc_cnt.sum(axis=0).astype(float) - c0
+    lam = p.ell * d[O.CNT_CHAINS] / (d[O.CNT_LIFTS] + d[O.CNT_FROZEN])
+    assert abs(lam - gold["lambda0_over_sigma"]) <= 0.005, lam
