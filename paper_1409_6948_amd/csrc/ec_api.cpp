@@ -427,8 +427,8 @@ ec_status ec_set_timing(ec_system s, int32_t on) {
   if (!on && s->timing) {
     EC_HIP(s, hipStreamSynchronize(s->stream));
     for (int q = 0; q < 4; ++q) {
-      hipEventDestroy(s->ev.begin[q]);
-      hipEventDestroy(s->ev.end[q]);
+      (void)hipEventDestroy(s->ev.begin[q]);
+      (void)hipEventDestroy(s->ev.end[q]);
     }
     s->timing = false;
   }
@@ -852,8 +852,8 @@ ec_status batch_sync_records(ec_batch b) {
     e = hipMemcpyAsync(b->sys[i]->dev_d, &h[i], sizeof(ec::Dev), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // h is a local
   if (b->graph_ready) {
-    hipGraphExecDestroy(b->exec);
-    hipGraphDestroy(b->graph);
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
     b->graph_ready = false;
   }
   if (e != hipSuccess) {
@@ -879,7 +879,7 @@ ec_status batch_sweeps(ec_batch b, int64_t n) {
       if (e != hipSuccess) return batch_fail(b, e, "end capture");
       e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
       if (e != hipSuccess) {
-        hipGraphDestroy(b->graph);
+        (void)hipGraphDestroy(b->graph);
         return batch_fail(b, e, "instantiate");
       }
       b->graph_ready = true;
@@ -1012,7 +1012,7 @@ ec_status ec_batch_autotune(ec_batch b, int32_t trial_sweeps, int32_t* cpb_out, 
   if (e != hipSuccess) return batch_fail(b, e, "snapshot");
   hipEvent_t t0, t1;
   if ((e = hipEventCreate(&t0)) != hipSuccess) return batch_fail(b, e, "event");
-  if ((e = hipEventCreate(&t1)) != hipSuccess) { hipEventDestroy(t0); return batch_fail(b, e, "event"); }
+  if ((e = hipEventCreate(&t1)) != hipSuccess) { (void)hipEventDestroy(t0); return batch_fail(b, e, "event"); }
   const int32_t cands[3] = {1, 2, 4};
   int32_t best = b->shape.cpb;
   double best_ms = 0.0;
@@ -1038,8 +1038,8 @@ ec_status ec_batch_autotune(ec_batch b, int32_t trial_sweeps, int32_t* cpb_out, 
     }
     if (ms_out) ms_out[c] = ms_c;
   }
-  hipEventDestroy(t0);
-  hipEventDestroy(t1);
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
   // back to the snapshot with the chosen schedule
   e = hipMemcpyAsync(sys0, snap, b->sys_bytes, hipMemcpyDeviceToDevice, b->stream);
   if (e != hipSuccess && st == EC_OK) st = batch_fail(b, e, "restore");
@@ -1057,8 +1057,8 @@ ec_status ec_destroy_batch(ec_batch b) {
   if (!b) return EC_E_INVALID;
   hipError_t e = hipStreamSynchronize(b->stream);
   if (b->graph_ready) {
-    hipGraphExecDestroy(b->exec);
-    hipGraphDestroy(b->graph);
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
   }
   for (auto* s : b->sys) {
     if (s->timing) { s->in_batch = false; ec_set_timing(s, 0); }
