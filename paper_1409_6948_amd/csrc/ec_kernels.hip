@@ -723,10 +723,19 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     int ended = 0;  // the chain length is used up
 
     while (ended == 0 && stop == 0 && n_events < (int)kMaxEventsPerChain) {
+      // the event found, and the decision (also read by the general path)
+      double tx, ty, best_s, wpx, wpy, e, step, nax, nay;
+      uint32_t wgid;
+      int w_lidx, w_bx, w_by, w_slot, packed;
+      // Plain lifts run in this inner loop, where the direction and its
+      // derived constants do not change: the general path, which can change
+      // them, sits outside it, so the common event needs no register copies
+      // where the two paths would otherwise join.
+      for (;;) {
       // walls of the cell: (wall - v) / d with 1/d precomputed, clamped at 0
-      double tx = (wallx - ax) * idxw;
+      tx = (wallx - ax) * idxw;
       tx = (tx < 0.0) ? 0.0 : tx;
-      double ty = (wally - ay) * idyw;
+      ty = (wally - ay) * idyw;
       ty = (ty < 0.0) ? 0.0 : ty;
 
       // -- contact distance of the disk in this lane's window slot
@@ -759,20 +768,18 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
 
       // the nearest disk (read from lane 0 when there is none; it is then unused)
       const int wls = wl < 0 ? 0 : wl;
-      double best_s = readlane_f64(s, wls);
+      best_s = readlane_f64(s, wls);
       const uint64_t mw = readlane_u64(m, wls);
-      uint32_t wgid = (uint32_t)mw;
-      int w_lidx = (int)(uint32_t)(mw >> 32);
-      double wpx = readlane_f64(p.x, wls);
-      double wpy = readlane_f64(p.y, wls);
+      wgid = (uint32_t)mw;
+      w_lidx = (int)(uint32_t)(mw >> 32);
+      wpx = readlane_f64(p.x, wls);
+      wpy = readlane_f64(p.y, wls);
       if (wl < 0) { best_s = INFINITY; wgid = 0xFFFFFFFFu; }
-      int w_bx = wx0 + (wls & 3);
-      int w_by = wy0 + ((wls >> 2) & 3);
-      int w_slot = ((w_by * gridb) + w_bx) * 4 + (wls >> 4);
+      w_bx = wx0 + (wls & 3);
+      w_by = wy0 + ((wls >> 2) & 3);
+      w_slot = ((w_by * gridb) + w_bx) * 4 + (wls >> 4);
 
       // the decision, made in vector registers and moved to the scalar unit once
-      int packed;
-      double e, step, nax, nay;
 #define EC_DECIDE(CHECK_WINDOW)                                                     \
       do {                                                                          \
         int kd = (best_s < INFINITY) ? ((wgid & kFrozenBit) ? EV_FROZEN : EV_LIFT) : 0; \
@@ -797,7 +804,8 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       // staying in its bin and chain length left over
       constexpr int kFastMask = (7 << 16) | (1 << 20) | (1 << 21) | (1 << 22);
       constexpr int kFast = (EV_LIFT << 16) | (1 << 21);
-      if (REJ == 0 && (packed & kFastMask) == kFast) {
+      if (REJ == 1 || (packed & kFastMask) != kFast) break;  // to the general path
+      {
         {
           const uint64_t sb = (uint64_t)__double_as_longlong(step);
           const uint32_t tag = ((uint32_t)EV_LIFT << 29) | (wgid & ~kFrozenBit);
@@ -833,7 +841,14 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         EC_WINDOW(abx, aby, xneg, yneg);
         p = pos[wbase + loff];
         m = meta[wbase + loff];
-      } else {
+      }
+      // event cap and abort polling (every value here is wave-uniform)
+      ++n_events;
+      if ((n_events & ((int)kAbortPollEvents - 1)) == 0) stop = uniform_i32(load_err(d));
+      if (stop != 0 || n_events >= (int)kMaxEventsPerChain) break;
+      }  // plain lifts
+      if (stop != 0 || n_events >= (int)kMaxEventsPerChain) continue;  // leaves the event loop
+      {
       if (((packed >> 21) & 1) == 0) {
         // the window cannot vouch for this event: exact search over every slot
         double ls = INFINITY;
