@@ -33,6 +33,7 @@ enum {
 constexpr int64_t kMaxEventsPerChain = int64_t(1) << 20;
 // Events between two polls of the device error word.
 constexpr int64_t kAbortPollEvents = 1024;
+static_assert(kMaxEventsPerChain % kAbortPollEvents == 0, "the event cap is tested at polls");
 // Attempts of one rejection draw (acceptance 0.785 for directions, > 1 - 2^-50
 // for indices); reaching the cap sets ERR_DRAW_CAP.
 constexpr int kMaxDrawTries = 256;

@@ -842,10 +842,13 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         p = pos[wbase + loff];
         m = meta[wbase + loff];
       }
-      // event cap and abort polling (every value here is wave-uniform)
+      // event cap and abort polling (every value here is wave-uniform); the
+      // cap is a multiple of the poll interval, so both are tested at polls
       ++n_events;
-      if ((n_events & ((int)kAbortPollEvents - 1)) == 0) stop = uniform_i32(load_err(d));
-      if (stop != 0 || n_events >= (int)kMaxEventsPerChain) break;
+      if ((n_events & ((int)kAbortPollEvents - 1)) == 0) {
+        stop = uniform_i32(load_err(d));
+        if (stop != 0 || n_events >= (int)kMaxEventsPerChain) break;
+      }
       }  // plain lifts
       if (stop != 0 || n_events >= (int)kMaxEventsPerChain) continue;  // leaves the event loop
       {
