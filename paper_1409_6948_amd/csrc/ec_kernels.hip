@@ -202,11 +202,14 @@ __device__ __forceinline__ unsigned wave_min_all(unsigned v) {
 __device__ __forceinline__ int wave_argmin_all(double s, uint32_t id, bool valid) {
   const uint64_t sb = (uint64_t)__double_as_longlong(s);
   const unsigned hi = valid ? (unsigned)(sb >> 32) : 0xFFFFFFFFu;
-  const unsigned m = wave_min_all(hi);
-  uint64_t mask = __builtin_amdgcn_ballot_w64(valid && hi == m);
-  if (mask == 0) return -1;
-  int wl = __ffsll((unsigned long long)mask) - 1;
-  if (__popcll(mask) > 1) {  // equal high words: resolve on the full key
+  const unsigned m = (unsigned)uniform_i32((int)wave_min_all(hi));
+  // a valid lane's high word (a non-negative distance) is never all ones, so
+  // m is all ones exactly when no lane is valid, and otherwise the lanes
+  // holding m are valid ones
+  if (m == 0xFFFFFFFFu) return -1;
+  uint64_t mask = __builtin_amdgcn_ballot_w64(hi == m);  // not empty: some lane holds m
+  int wl = __builtin_ctzll(mask);
+  if (mask != (1ull << wl)) {  // equal high words: resolve on the full key
     mask &= mask - 1;
     uint64_t bs = readlane_u64(sb, wl);
     uint32_t bi = (uint32_t)readlane_i32((int)id, wl);
@@ -727,6 +730,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       double tx, ty, best_s, wpx, wpy, e, step, nax, nay;
       uint32_t wgid;
       int w_lidx, w_bx, w_by, w_slot, packed;
+      int found;  // a disk can be hit (wave-uniform)
       // Plain lifts run in this inner loop, where the direction and its
       // derived constants do not change: the general path, which can change
       // them, sits outside it, so the common event needs no register copies
@@ -774,6 +778,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       w_lidx = (int)(uint32_t)(mw >> 32);
       wpx = readlane_f64(p.x, wls);
       wpy = readlane_f64(p.y, wls);
+      found = wl >= 0 ? 1 : 0;
       if (wl < 0) { best_s = INFINITY; wgid = 0xFFFFFFFFu; }
       w_bx = wx0 + (wls & 3);
       w_by = wy0 + ((wls >> 2) & 3);
@@ -782,7 +787,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       // the decision, made in vector registers and moved to the scalar unit once
 #define EC_DECIDE(CHECK_WINDOW)                                                     \
       do {                                                                          \
-        int kd = (best_s < INFINITY) ? ((wgid & kFrozenBit) ? EV_FROZEN : EV_LIFT) : 0; \
+        int kd = found ? ((wgid & kFrozenBit) ? EV_FROZEN : EV_LIFT) : 0;          \
         e = best_s;                                                                 \
         if (tx < e) { e = tx; kd = EV_WALL_X; }                                     \
         if (ty < e) { e = ty; kd = EV_WALL_Y; }                                     \
@@ -866,6 +871,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
           }
         }
         const int fl = wave_argmin_all(ls, lid, lslot >= 0);
+        found = fl >= 0 ? 1 : 0;
         best_s = INFINITY;
         wgid = 0xFFFFFFFFu;
         if (fl >= 0) {
