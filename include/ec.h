@@ -106,7 +106,7 @@ typedef struct {
   uint32_t flags;           /* EC_FLAG_* bits, 0 = default                                  */
   int64_t  n_disks;         /* N; the lattice start needs N = k*k with k even; walled cells
                                (C > 1) take N <= 2^29 - 4 (EC_E_UNSUPPORTED above)       */
-  double   sigma;           /* disk diameter, > 0                                           */
+  double   sigma;           /* disk diameter, in [2^-300, 2^300]                            */
   double   eta;             /* 0 < eta < pi/(2 sqrt 3); L = sigma sqrt(N pi / (4 eta))       */
   double   ell;             /* displacement of one chain, > 0                               */
   int32_t  cells_per_side;  /* C: 1 = one periodic cell without walls; else even, >= 4,

@@ -86,7 +86,9 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
   if (!p) { *why = "null parameters"; return EC_E_INVALID; }
   if (p->abi_version != EC_ABI_VERSION) { *why = "abi_version mismatch"; return EC_E_INVALID; }
   if (p->n_disks < 1 || p->n_disks > 0x7FFFFFF0LL) { *why = "n_disks out of range"; return EC_E_INVALID; }
-  if (!(p->sigma > 0.0) || !std::isfinite(p->sigma)) { *why = "sigma must be > 0"; return EC_E_INVALID; }
+  if (!(p->sigma >= 0x1p-300) || !(p->sigma <= 0x1p300)) {
+    *why = "sigma must be in [2^-300, 2^300]"; return EC_E_INVALID;
+  }
   if ((p->flags & EC_FLAG_REJECT) &&
       (p->cells_per_side == 1 || p->precision != EC_PREC_FP64)) {
     *why = "EC_FLAG_REJECT needs walled cells and FP64"; return EC_E_UNSUPPORTED;

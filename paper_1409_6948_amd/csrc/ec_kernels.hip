@@ -274,17 +274,37 @@ enum { EV_LIFT = 1, EV_FROZEN = 2, EV_WALL_X = 3, EV_WALL_Y = 4, EV_PSEUDO = 5, 
 // Contact distance of a disk moving along unit d towards a disk at offset r:
 // s = a - sqrt(sigma^2 - c^2) with a = r.d, c = r x d, for a > 0 and
 // sigma^2 - c^2 > 0; negative values (touching disks) become 0.
+// Correctly rounded square root of x in [2^-767, 2^1000] (Markstein's
+// method: the hardware reciprocal square root estimate, one Newton step on
+// (g, h) = (x y, y/2), then two corrections with the exact residual x - g^2
+// from a fused multiply-add; P. Markstein, IBM J. Res. Dev. 34 (1990) 111).
+// The general sqrt() adds range scaling and special-value selects; the
+// contact term's argument sigma^2 - c^2, where positive, is at least about
+// 2^-106 sigma^2, and sigma is limited to [2^-300, 2^300], so x stays in range.
+__device__ __forceinline__ double sqrt_contact(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = 0.5 * y;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double dd = fma(-g, g, x);
+  g = fma(dd, h, g);
+  dd = fma(-g, g, x);
+  return fma(dd, h, g);
+}
+
 __device__ __forceinline__ bool contact(double rx, double ry, double dx, double dy, double sig2,
                                         double& s) {
   double a = fma(rx, dx, ry * dy);
   double c = fma(rx, dy, -(ry * dx));
   double disc = fma(-c, c, sig2);
-  if (a > 0.0 && disc > 0.0) {
-    double t = a - sqrt(disc);
-    s = (t < 0.0) ? 0.0 : t;
-    return true;
-  }
-  return false;
+  // computed in every lane and selected (no branch): where disc <= 0 the
+  // root is NaN or infinite and the lane is not a candidate
+  const bool ok = a > 0.0 && disc > 0.0;
+  const double t = a - sqrt_contact(disc);
+  s = ok ? ((t < 0.0) ? 0.0 : t) : s;
+  return ok;
 }
 
 // Shifted-frame coordinate in [0, L] and cell-local coordinate.
