@@ -754,8 +754,10 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       // Plain lifts run in this inner loop, where the direction and its
       // derived constants do not change: the general path, which can change
       // them, sits outside it, so the common event needs no register copies
-      // where the two paths would otherwise join.
-      for (;;) {
+      // where the two paths would otherwise join.  One exit, on a uniform
+      // integer (go: 1 after a plain lift while no poll has stopped).
+      int go = 1;
+      while (go != 0) {
       // walls of the cell: (wall - v) / d with 1/d precomputed, clamped at 0
       tx = (wallx - ax) * idxw;
       tx = (tx < 0.0) ? 0.0 : tx;
@@ -829,8 +831,8 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       // staying in its bin and chain length left over
       constexpr int kFastMask = (7 << 16) | (1 << 20) | (1 << 21) | (1 << 22);
       constexpr int kFast = (EV_LIFT << 16) | (1 << 21);
-      if (REJ == 1 || (packed & kFastMask) != kFast) break;  // to the general path
-      {
+      go = (REJ == 0 && (packed & kFastMask) == kFast) ? 1 : 0;  // else to the general path
+      if (go != 0) {
         {
           const uint64_t sb = (uint64_t)__double_as_longlong(step);
           const uint32_t tag = ((uint32_t)EV_LIFT << 29) | (wgid & ~kFrozenBit);
@@ -866,13 +868,13 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         EC_WINDOW(abx, aby, xneg, yneg);
         p = pos[wbase + loff];
         m = meta[wbase + loff];
-      }
-      // event cap and abort polling (every value here is wave-uniform); the
-      // cap is a multiple of the poll interval, so both are tested at polls
-      ++n_events;
-      if ((n_events & ((int)kAbortPollEvents - 1)) == 0) {
-        stop = uniform_i32(load_err(d));
-        if (stop != 0 || n_events >= (int)kMaxEventsPerChain) break;
+        // event cap and abort polling (every value here is wave-uniform); the
+        // cap is a multiple of the poll interval, so both are tested at polls
+        ++n_events;
+        if ((n_events & ((int)kAbortPollEvents - 1)) == 0) {
+          stop = uniform_i32(load_err(d));
+          go = (stop == 0 && n_events < (int)kMaxEventsPerChain) ? 1 : 0;
+        }
       }
       }  // plain lifts
       if (stop != 0 || n_events >= (int)kMaxEventsPerChain) continue;  // leaves the event loop
