@@ -817,9 +817,12 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         step = en ? rem : e;                                                        \
         nax = fma(step, dx, ax);                                                    \
         nay = fma(step, dy, ay);                                                    \
-        /* truncation equals floor for x >= 0; below 0 both clamp to bin 1 */      \
-        const int bx_ = min(max((int)(nax * inv_b) + 1, 1), nb);                    \
-        const int by_ = min(max((int)(nay * inv_b) + 1, 1), nb);                    \
+        /* bin of the moved centre, unclamped: a centre lies in [0, w], where    */ \
+        /* truncation gives bins 1..nb, and nb + 1 only on the far wall (or one  */ \
+        /* rounding past it); that case counts as a bin change and the general   */ \
+        /* path clamps it                                                       */ \
+        const int bx_ = (int)(nax * inv_b) + 1;                                     \
+        const int by_ = (int)(nay * inv_b) + 1;                                     \
         bool ok_ = true;                                                            \
         if (CHECK_WINDOW) ok_ = step <= dsafe;                                      \
         const int cr_ = (bx_ != abx || by_ != aby) ? 1 : 0;                          \
@@ -915,7 +918,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
 #undef EC_DECIDE
       const int kind = (packed >> 16) & 7;
       const bool ends = ((packed >> 20) & 1) != 0;
-      const int nbx = packed & 0xFF, nby = (packed >> 8) & 0xFF;
+      const int nbx = min(packed & 0xFF, nb), nby = min((packed >> 8) & 0xFF, nb);
       // REJ 1: a wall or a frozen disk rejects the chain
       const bool rejected = REJ == 1 && !ends && kind != EV_LIFT;
       const double pax = ax, pay = ay;  // position before this event's move
