@@ -131,15 +131,18 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ unsigned umin_(unsigned a, unsigned b) { return a < b ? a : b; }
 
-// Minimum of a 32-bit value over the 64 lanes (DPP butterfly within rows of
-// 16, then row broadcasts); every lane gets the result.
+// Minimum of a 32-bit value over the 64 lanes as a scalar: DPP steps within
+// rows of 16, then the row broadcasts of lane 15 into rows 1 and 3 and of
+// lane 31 into rows 2 and 3, which leave the minimum in lane 63.
 __device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
-  v = umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));
-  v = umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));
-  v = umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));
-  v = umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));
-  v = umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));
-  v = umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));
+  v = umin_(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true));
+  v = umin_(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true));
+  v = umin_(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true));
+  v = umin_(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true));
+  // rows outside a broadcast's mask may take any value: only rows 1 and 3
+  // (then row 3) are read afterwards
+  v = umin_(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x142, 0xA, 0xF, false));
+  v = umin_(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x143, 0xC, 0xF, false));
   return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
@@ -202,7 +205,7 @@ __device__ __forceinline__ unsigned wave_min_all(unsigned v) {
 __device__ __forceinline__ int wave_argmin_all(double s, uint32_t id, bool valid) {
   const uint64_t sb = (uint64_t)__double_as_longlong(s);
   const unsigned hi = valid ? (unsigned)(sb >> 32) : 0xFFFFFFFFu;
-  const unsigned m = (unsigned)uniform_i32((int)wave_min_all(hi));
+  const unsigned m = wave_min_u32(hi);
   // a valid lane's high word (a non-negative distance) is never all ones, so
   // m is all ones exactly when no lane is valid, and otherwise the lanes
   // holding m are valid ones
