@@ -832,15 +832,23 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         packed = uniform_i32(bx_ | (by_ << 8) | (kd << 16) | ((en ? 1 : 0) << 20) | \
                              ((ok_ ? 1 : 0) << 21) | (cr_ << 22));                  \
       } while (0)
-      EC_DECIDE(true);
-      // the common event: a lift the window vouches for, with the moved disk
-      // staying in its bin and chain length left over
-      constexpr int kFastMask = (7 << 16) | (1 << 20) | (1 << 21) | (1 << 22);
-      constexpr int kFast = (EV_LIFT << 16) | (1 << 21);
-      go = (REJ == 0 && (packed & kFastMask) == kFast) ? 1 : 0;  // else to the general path
+      // The common event, tested directly on the nearest disk: a disk (not
+      // frozen) is hit before either wall (a wall wins only when strictly
+      // nearer), chain length is left over, the window vouches for the move
+      // and the moved centre stays in its bin.  This is exactly the full
+      // decision (EC_DECIDE) finding such a lift; the general path makes the
+      // full decision for every other event.
+      nax = fma(best_s, dx, ax);
+      nay = fma(best_s, dy, ay);
+      {
+        const int plain = (found != 0) & ((wgid & kFrozenBit) == 0) & !(tx < best_s) &
+                          !(ty < best_s) & (best_s < rem) & (best_s <= dsafe) &
+                          ((int)(nax * inv_b) + 1 == abx) & ((int)(nay * inv_b) + 1 == aby);
+        go = (REJ == 0 && uniform_i32(plain) != 0) ? 1 : 0;  // else to the general path
+      }
       if (go != 0) {
         {
-          const uint64_t sb = (uint64_t)__double_as_longlong(step);
+          const uint64_t sb = (uint64_t)__double_as_longlong(best_s);
           const uint32_t tag = ((uint32_t)EV_LIFT << 29) | (wgid & ~kFrozenBit);
           const bool mine = lane == n_ring;
           rec_lo = mine ? (uint32_t)sb : rec_lo;
@@ -863,7 +871,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         }
         acc = acc + fma(wpx - nax, dx, (wpy - nay) * dy);
         n_lift += 1;
-        rem = rem - e;
+        rem = rem - best_s;
         a_loc = w_slot;
         a_gid = wgid;
         a_lidx = w_lidx;
@@ -885,6 +893,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       }  // plain lifts
       if (stop != 0 || n_events >= (int)kMaxEventsPerChain) continue;  // leaves the event loop
       {
+      EC_DECIDE(true);
       if (((packed >> 21) & 1) == 0) {
         // the window cannot vouch for this event: exact search over every slot
         double ls = INFINITY;
