@@ -162,6 +162,18 @@ __device__ __forceinline__ int readlane_i32(int v, int lane) {
 // this: compiled as a divergent if/else chain on a vector register, one of
 // its arms (the y-wall reflection) lost its direction update.
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Lane `lane` of a, b, c replaced by the wave-uniform values va, vb, vc
+// (v_writelane, lane select in M0: no compare and no change of the execution
+// mask)
+__device__ __forceinline__ void writelane3(uint32_t& a, uint32_t& b, uint32_t& c, uint32_t va,
+                                           uint32_t vb, uint32_t vc, int lane) {
+  asm("v_writelane_b32 %0, %3, m0\n\t"
+      "v_writelane_b32 %1, %4, m0\n\t"
+      "v_writelane_b32 %2, %5, m0"
+      : "+v"(a), "+v"(b), "+v"(c)
+      : "s"(uniform_i32((int)va)), "s"(uniform_i32((int)vb)), "s"(uniform_i32((int)vc)),
+        "{m0}"(lane));
+}
 
 // Lane holding the smallest key (s, id) among lanes with valid = true, where
 // s >= 0 so that its bit pattern orders like its value.  -1 if none.
@@ -202,14 +214,15 @@ __device__ __forceinline__ unsigned wave_min_all(unsigned v) {
 }
 
 // As wave_argmin, with the minimum of the high words kept in every lane.
-__device__ __forceinline__ int wave_argmin_all(double s, uint32_t id, bool valid) {
+// The argmin in two steps: argmin_key is the lane's key (the high word of s
+// on valid lanes, all ones elsewhere); its wave minimum m is all ones exactly
+// when no lane is valid, since a valid lane's high word (a non-negative
+// distance) never is.  Given m below all ones, argmin_lane returns the lane.
+__device__ __forceinline__ unsigned argmin_key(double s, bool valid) {
+  return valid ? (unsigned)((uint64_t)__double_as_longlong(s) >> 32) : 0xFFFFFFFFu;
+}
+__device__ __forceinline__ int argmin_lane(double s, uint32_t id, unsigned hi, unsigned m) {
   const uint64_t sb = (uint64_t)__double_as_longlong(s);
-  const unsigned hi = valid ? (unsigned)(sb >> 32) : 0xFFFFFFFFu;
-  const unsigned m = wave_min_u32(hi);
-  // a valid lane's high word (a non-negative distance) is never all ones, so
-  // m is all ones exactly when no lane is valid, and otherwise the lanes
-  // holding m are valid ones
-  if (m == 0xFFFFFFFFu) return -1;
   uint64_t mask = __builtin_amdgcn_ballot_w64(hi == m);  // not empty: some lane holds m
   int wl = __builtin_ctzll(mask);
   if (mask != (1ull << wl)) {  // equal high words: resolve on the full key
@@ -225,6 +238,12 @@ __device__ __forceinline__ int wave_argmin_all(double s, uint32_t id, bool valid
     }
   }
   return wl;
+}
+__device__ __forceinline__ int wave_argmin_all(double s, uint32_t id, bool valid) {
+  const unsigned hi = argmin_key(s, valid);
+  const unsigned m = wave_min_u32(hi);
+  if (m == 0xFFFFFFFFu) return -1;
+  return argmin_lane(s, id, hi, m);
 }
 
 // Event digest (a test device, not part of the method).  Event i of a cell's
@@ -744,8 +763,9 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     uint32_t chain_lifts = 0;
     int wx0, wy0, wbase;
     EC_WINDOW(abx, aby, xneg, yneg);
-    double2 p = pos[wbase + loff];
-    uint64_t m = meta[wbase + loff];
+    int widx = wbase + loff;  // this lane's slot in the window
+    double2 p = pos[widx];
+    uint64_t m = meta[widx];
     int ended = 0;  // the chain length is used up
 
     while (ended == 0 && stop == 0 && n_events < (int)kMaxEventsPerChain) {
@@ -760,12 +780,16 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       // where the two paths would otherwise join.  One exit, on a uniform
       // integer (go: 1 after a plain lift while no poll has stopped).
       int go = 1;
+      // distances to the walls of the cell ahead: (wall - v) / d with 1/d
+      // precomputed, clamped at 0
+#define EC_WALLS()                                                                  \
+      do {                                                                          \
+        tx = (wallx - ax) * idxw;                                                   \
+        tx = (tx < 0.0) ? 0.0 : tx;                                                 \
+        ty = (wally - ay) * idyw;                                                   \
+        ty = (ty < 0.0) ? 0.0 : ty;                                                 \
+      } while (0)
       while (go != 0) {
-      // walls of the cell: (wall - v) / d with 1/d precomputed, clamped at 0
-      tx = (wallx - ax) * idxw;
-      tx = (tx < 0.0) ? 0.0 : tx;
-      ty = (wally - ay) * idyw;
-      ty = (ty < 0.0) ? 0.0 : ty;
 
       // -- contact distance of the disk in this lane's window slot
       double s = 0.0;
@@ -793,21 +817,28 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         valid = false;
         if (survivor) valid = contact(p.x - ax, p.y - ay, dx, dy, sig2, s);
       }
-      const int wl = wave_argmin_all(s, (uint32_t)m & ~kFrozenBit, valid);
-
-      // the nearest disk (read from lane 0 when there is none; it is then unused)
-      const int wls = wl < 0 ? 0 : wl;
+      const unsigned key = argmin_key(s, valid);
+      const unsigned key_min = wave_min_u32(key);
+      found = key_min != 0xFFFFFFFFu ? 1 : 0;
+      if (found == 0) {
+        // no disk in the window: the general path decides (a wall, the chain
+        // end, or, where the window cannot vouch, a search of every slot);
+        // the nearest disk's other values are read there only for a disk
+        best_s = INFINITY;
+        wgid = 0xFFFFFFFFu;
+        go = 0;
+      } else {
+      // the nearest disk
+      const int wls = argmin_lane(s, (uint32_t)m & ~kFrozenBit, key, key_min);
       best_s = readlane_f64(s, wls);
       const uint64_t mw = readlane_u64(m, wls);
       wgid = (uint32_t)mw;
       w_lidx = (int)(uint32_t)(mw >> 32);
       wpx = readlane_f64(p.x, wls);
       wpy = readlane_f64(p.y, wls);
-      found = wl >= 0 ? 1 : 0;
-      if (wl < 0) { best_s = INFINITY; wgid = 0xFFFFFFFFu; }
       w_bx = wx0 + (wls & 3);
       w_by = wy0 + ((wls >> 2) & 3);
-      w_slot = ((w_by * gridb) + w_bx) * 4 + (wls >> 4);
+      w_slot = readlane_i32(widx, wls);
 
       // the decision, made in vector registers and moved to the scalar unit once
 #define EC_DECIDE(CHECK_WINDOW)                                                     \
@@ -841,19 +872,24 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       nax = fma(best_s, dx, ax);
       nay = fma(best_s, dy, ay);
       {
-        const int plain = (found != 0) & ((wgid & kFrozenBit) == 0) & !(tx < best_s) &
-                          !(ty < best_s) & (best_s < rem) & (best_s <= dsafe) &
-                          ((int)(nax * inv_b) + 1 == abx) & ((int)(nay * inv_b) + 1 == aby);
+        int plain = ((wgid & kFrozenBit) == 0) & (best_s < rem) &
+                    (best_s <= dsafe) & ((int)(nax * inv_b) + 1 == abx) &
+                    ((int)(nay * inv_b) + 1 == aby);
+        // A moved centre that stays in a bin not bordering the wall ahead is
+        // at least one bin width short of that wall, a margin far beyond the
+        // rounding of the distances compared: only from the bins along the
+        // walls ahead can a wall come first.
+        if (abx == (xneg ? 1 : nb) || aby == (yneg ? 1 : nb)) {
+          EC_WALLS();
+          plain &= (int)!(tx < best_s) & (int)!(ty < best_s);
+        }
         go = (REJ == 0 && uniform_i32(plain) != 0) ? 1 : 0;  // else to the general path
       }
       if (go != 0) {
         {
           const uint64_t sb = (uint64_t)__double_as_longlong(best_s);
           const uint32_t tag = ((uint32_t)EV_LIFT << 29) | (wgid & ~kFrozenBit);
-          const bool mine = lane == n_ring;
-          rec_lo = mine ? (uint32_t)sb : rec_lo;
-          rec_hi = mine ? (uint32_t)(sb >> 32) : rec_hi;
-          rec_tag = mine ? tag : rec_tag;
+          writelane3(rec_lo, rec_hi, rec_tag, (uint32_t)sb, (uint32_t)(sb >> 32), tag, n_ring);
         }
         {
           double2* const dst = (lane == 0) ? pos + a_loc : sink;
@@ -880,8 +916,9 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         ax = wpx;
         ay = wpy;
         EC_WINDOW(abx, aby, xneg, yneg);
-        p = pos[wbase + loff];
-        m = meta[wbase + loff];
+        widx = wbase + loff;
+        p = pos[widx];
+        m = meta[widx];
         // event cap and abort polling (every value here is wave-uniform); the
         // cap is a multiple of the poll interval, so both are tested at polls
         ++n_events;
@@ -890,9 +927,11 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
           go = (stop == 0 && n_events < (int)kMaxEventsPerChain) ? 1 : 0;
         }
       }
+      }  // a disk in the window
       }  // plain lifts
       if (stop != 0 || n_events >= (int)kMaxEventsPerChain) continue;  // leaves the event loop
       {
+      EC_WALLS();
       EC_DECIDE(true);
       if (((packed >> 21) & 1) == 0) {
         // the window cannot vouch for this event: exact search over every slot
@@ -928,6 +967,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         EC_DECIDE(false);
       }
 #undef EC_DECIDE
+#undef EC_WALLS
       const int kind = (packed >> 16) & 7;
       const bool ends = ((packed >> 20) & 1) != 0;
       const int nbx = min(packed & 0xFF, nb), nby = min((packed >> 8) & 0xFF, nb);
@@ -942,14 +982,11 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
                                                      : (kind == EV_WALL_Y ? (uint32_t)wall_y_id
                                                                           : (wgid & ~kFrozenBit)));
       {
-        // lane n_ring keeps this event's record (a select, no change of the
-        // execution mask)
+        // lane n_ring keeps this event's record (lane writes, no change of
+        // the execution mask)
         const uint64_t sb = (uint64_t)__double_as_longlong(step);
         const uint32_t tag = ((uint32_t)(ends ? EV_END : kind) << 29) | eid;
-        const bool mine = lane == n_ring;
-        rec_lo = mine ? (uint32_t)sb : rec_lo;
-        rec_hi = mine ? (uint32_t)(sb >> 32) : rec_hi;
-        rec_tag = mine ? tag : rec_tag;
+        writelane3(rec_lo, rec_hi, rec_tag, (uint32_t)sb, (uint32_t)(sb >> 32), tag, n_ring);
       }
       if (REJ == 1 && !rejected && !ends) {
         // log the lift's move: slot before it and old position (the slot after
@@ -1086,8 +1123,9 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       // window of the next event (the stores above are seen: LDS operations
       // of one wave complete in order)
       EC_WINDOW(abx, aby, xneg, yneg);
-      p = pos[wbase + loff];
-      m = meta[wbase + loff];
+      widx = wbase + loff;
+      p = pos[widx];
+      m = meta[widx];
       }
       // event cap and abort polling (every value here is wave-uniform)
       ++n_events;
