@@ -225,7 +225,7 @@ __device__ __forceinline__ int argmin_lane(double s, uint32_t id, unsigned hi, u
   const uint64_t sb = (uint64_t)__double_as_longlong(s);
   uint64_t mask = __builtin_amdgcn_ballot_w64(hi == m);  // not empty: some lane holds m
   int wl = __builtin_ctzll(mask);
-  if (mask != (1ull << wl)) {  // equal high words: resolve on the full key
+  if (__builtin_expect(mask != (1ull << wl), 0)) {  // equal high words: resolve on the full key
     mask &= mask - 1;
     uint64_t bs = readlane_u64(sb, wl);
     uint32_t bi = (uint32_t)readlane_i32((int)id, wl);
@@ -820,7 +820,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       const unsigned key = argmin_key(s, valid);
       const unsigned key_min = wave_min_u32(key);
       found = key_min != 0xFFFFFFFFu ? 1 : 0;
-      if (found == 0) {
+      if (__builtin_expect(found == 0, 0)) {
         // no disk in the window: the general path decides (a wall, the chain
         // end, or, where the window cannot vouch, a search of every slot);
         // the nearest disk's other values are read there only for a disk
@@ -879,13 +879,13 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         // at least one bin width short of that wall, a margin far beyond the
         // rounding of the distances compared: only from the bins along the
         // walls ahead can a wall come first.
-        if (abx == (xneg ? 1 : nb) || aby == (yneg ? 1 : nb)) {
+        if (__builtin_expect(abx == (xneg ? 1 : nb) || aby == (yneg ? 1 : nb), 0)) {
           EC_WALLS();
           plain &= (int)!(tx < best_s) & (int)!(ty < best_s);
         }
         go = (REJ == 0 && uniform_i32(plain) != 0) ? 1 : 0;  // else to the general path
       }
-      if (go != 0) {
+      if (__builtin_expect(go != 0, 1)) {
         {
           const uint64_t sb = (uint64_t)__double_as_longlong(best_s);
           const uint32_t tag = ((uint32_t)EV_LIFT << 29) | (wgid & ~kFrozenBit);
@@ -900,7 +900,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
           }
         }
         __builtin_amdgcn_wave_barrier();
-        if (++n_ring == kDigestBatch) {
+        if (__builtin_expect(++n_ring == kDigestBatch, 0)) {
           h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first);
           ring_first += kDigestBatch;
           n_ring = 0;
@@ -922,7 +922,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         // event cap and abort polling (every value here is wave-uniform); the
         // cap is a multiple of the poll interval, so both are tested at polls
         ++n_events;
-        if ((n_events & ((int)kAbortPollEvents - 1)) == 0) {
+        if (__builtin_expect((n_events & ((int)kAbortPollEvents - 1)) == 0, 0)) {
           stop = uniform_i32(load_err(d));
           go = (stop == 0 && n_events < (int)kMaxEventsPerChain) ? 1 : 0;
         }
