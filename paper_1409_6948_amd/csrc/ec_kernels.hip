@@ -933,7 +933,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       {
       EC_WALLS();
       EC_DECIDE(true);
-      if (((packed >> 21) & 1) == 0) {
+      if (__builtin_expect(((packed >> 21) & 1) == 0, 0)) {
         // the window cannot vouch for this event: exact search over every slot
         double ls = INFINITY;
         uint32_t lid = 0xFFFFFFFFu;
@@ -1034,7 +1034,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         const int abin = aby * gridb + abx, nbin = nby * gridb + nbx;
         const int nm = uniform_i32(mask[nbin]);
         const int free_slot = __builtin_ctz((unsigned)(~nm & 0xF) | 0x10u);
-        if (free_slot >= 4) {
+        if (__builtin_expect(free_slot >= 4, 0)) {
           if (lane == 0) {
             atomicOr(d.err, ERR_BIN_CAP);
             pos[a_loc] = make_double2(ax, ay);
@@ -1064,7 +1064,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         n_undo += 1;
       }
       __builtin_amdgcn_wave_barrier();
-      if (++n_ring == kDigestBatch) {
+      if (__builtin_expect(++n_ring == kDigestBatch, 0)) {
         h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first);
         ring_first += kDigestBatch;
         n_ring = 0;
@@ -1088,7 +1088,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         aby = w_by;
         ax = wpx;
         ay = wpy;
-      } else if (ends) {
+      } else if (__builtin_expect(ends, 0)) {
         ended = 1;
         if (REJ == 1) {  // accepted: its contact sum and lifts count
           acc = acc + chain_acc;
@@ -1096,7 +1096,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         }
       } else {
         rem = rem - e;
-        if (kind == EV_FROZEN) {
+        if (__builtin_expect(kind == EV_FROZEN, 1)) {
           // mirror the direction about the contact normal
           const double rx = wpx - ax, ry = wpy - ay;
           acc = acc + fma(rx, dx, ry * dy);
@@ -1129,7 +1129,8 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       }
       // event cap and abort polling (every value here is wave-uniform)
       ++n_events;
-      if ((n_events & ((int)kAbortPollEvents - 1)) == 0) stop = uniform_i32(load_err(d));
+      if (__builtin_expect((n_events & ((int)kAbortPollEvents - 1)) == 0, 0))
+        stop = uniform_i32(load_err(d));
     }
     if (ended == 0) {
       // stopped by another wave's error, or this chain reached the event cap
