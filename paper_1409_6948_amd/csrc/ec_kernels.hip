@@ -789,7 +789,10 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         ty = (wally - ay) * idyw;                                                   \
         ty = (ty < 0.0) ? 0.0 : ty;                                                 \
       } while (0)
-      while (go != 0) {
+      // One plain-lift event (or, on any other event, the exit to the general
+      // path with go = 0); the loop runs two per pass, so that the common
+      // event takes a taken branch only every other time.
+      auto plain_event = [&]() __attribute__((always_inline)) {
 
       // -- contact distance of the disk in this lane's window slot
       double s = 0.0;
@@ -928,6 +931,11 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         }
       }
       }  // a disk in the window
+      };
+      while (go != 0) {
+        plain_event();
+        if (__builtin_expect(go == 0, 0)) break;
+        plain_event();
       }  // plain lifts
       if (stop != 0 || n_events >= (int)kMaxEventsPerChain) continue;  // leaves the event loop
       {
