@@ -820,6 +820,15 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         valid = false;
         if (survivor) valid = contact(p.x - ax, p.y - ay, dx, dy, sig2, s);
       }
+      // The plain-lift test (below) of every lane's own candidate, made
+      // while the wave minimum is formed; the winning lane's result is read.
+      int plain_l;
+      {
+        const double nxl = fma(s, dx, ax), nyl = fma(s, dy, ay);
+        plain_l = (int)(((uint32_t)m & kFrozenBit) == 0) & (int)(s < rem) & (int)(s <= dsafe) &
+                  (int)((int)(nxl * inv_b) + 1 == abx) & (int)((int)(nyl * inv_b) + 1 == aby);
+        asm volatile("" : : "v"(plain_l));  // keep it here, beside the wave minimum
+      }
       const unsigned key = argmin_key(s, valid);
       const unsigned key_min = wave_min_u32(key);
       found = key_min != 0xFFFFFFFFu ? 1 : 0;
@@ -875,9 +884,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       nax = fma(best_s, dx, ax);
       nay = fma(best_s, dy, ay);
       {
-        int plain = ((wgid & kFrozenBit) == 0) & (best_s < rem) &
-                    (best_s <= dsafe) & ((int)(nax * inv_b) + 1 == abx) &
-                    ((int)(nay * inv_b) + 1 == aby);
+        int plain = readlane_i32(plain_l, wls);
         // A moved centre that stays in a bin not bordering the wall ahead is
         // at least one bin width short of that wall, a margin far beyond the
         // rounding of the distances compared: only from the bins along the
