@@ -756,7 +756,11 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     const double2 ap = pos[a_loc];
     double ax = ap.x, ay = ap.y;
     double rem = d.ell;
-    int n_events = 0;
+    // event cap and abort polling: events left until the next poll, and polls
+    // made (the cap is a whole number of poll intervals, so it is met at a poll)
+    constexpr int kMaxPolls = (int)(kMaxEventsPerChain / kAbortPollEvents);
+    int poll_left = (int)kAbortPollEvents;
+    int n_polls = 0;
     // REJ 1: the chain's undo log, contact sum and lifts (counted once accepted)
     int n_undo = 0;
     double chain_acc = 0.0;
@@ -768,7 +772,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     uint64_t m = meta[widx];
     int ended = 0;  // the chain length is used up
 
-    while (ended == 0 && stop == 0 && n_events < (int)kMaxEventsPerChain) {
+    while (ended == 0 && stop == 0 && n_polls < kMaxPolls) {
       // the event found, and the decision (also read by the general path)
       double tx, ty, best_s, wpx, wpy, e, step, nax, nay;
       uint32_t wgid;
@@ -891,9 +895,9 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         // walls ahead can a wall come first.
         if (__builtin_expect(abx == (xneg ? 1 : nb) || aby == (yneg ? 1 : nb), 0)) {
           EC_WALLS();
-          plain &= (int)!(tx < best_s) & (int)!(ty < best_s);
+          plain &= uniform_i32((int)!(tx < best_s) & (int)!(ty < best_s));
         }
-        go = (REJ == 0 && uniform_i32(plain) != 0) ? 1 : 0;  // else to the general path
+        go = (REJ == 0 && plain != 0) ? 1 : 0;  // else to the general path
       }
       if (__builtin_expect(go != 0, 1)) {
         {
@@ -929,12 +933,12 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         widx = wbase + loff;
         p = pos[widx];
         m = meta[widx];
-        // event cap and abort polling (every value here is wave-uniform); the
-        // cap is a multiple of the poll interval, so both are tested at polls
-        ++n_events;
-        if (__builtin_expect((n_events & ((int)kAbortPollEvents - 1)) == 0, 0)) {
+        // event cap and abort polling (every value here is wave-uniform)
+        if (__builtin_expect(--poll_left == 0, 0)) {
+          poll_left = (int)kAbortPollEvents;
+          ++n_polls;
           stop = uniform_i32(load_err(d));
-          go = (stop == 0 && n_events < (int)kMaxEventsPerChain) ? 1 : 0;
+          go = (stop == 0 && n_polls < kMaxPolls) ? 1 : 0;
         }
       }
       }  // a disk in the window
@@ -944,7 +948,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         if (__builtin_expect(go == 0, 0)) break;
         plain_event();
       }  // plain lifts
-      if (stop != 0 || n_events >= (int)kMaxEventsPerChain) continue;  // leaves the event loop
+      if (stop != 0 || n_polls >= kMaxPolls) continue;  // leaves the event loop
       {
       EC_WALLS();
       EC_DECIDE(true);
@@ -1143,9 +1147,11 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       m = meta[widx];
       }
       // event cap and abort polling (every value here is wave-uniform)
-      ++n_events;
-      if (__builtin_expect((n_events & ((int)kAbortPollEvents - 1)) == 0, 0))
+      if (__builtin_expect(--poll_left == 0, 0)) {
+        poll_left = (int)kAbortPollEvents;
+        ++n_polls;
         stop = uniform_i32(load_err(d));
+      }
     }
     if (ended == 0) {
       // stopped by another wave's error, or this chain reached the event cap
