@@ -744,8 +744,8 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     do {                                                                            \
       wx0 = (bx) - 1 - (xn);                                                        \
       wy0 = (by) - 1 - (yn);                                                        \
-      wx0 = wx0 < 0 ? 0 : (wx0 > gridb - 4 ? gridb - 4 : wx0);                      \
-      wy0 = wy0 < 0 ? 0 : (wy0 > gridb - 4 ? gridb - 4 : wy0);                      \
+      wx0 = max(min(wx0, gridb - 4), 0);                                            \
+      wy0 = max(min(wy0, gridb - 4), 0);                                            \
       wbase = (wy0 * gridb + wx0) * 4;                                              \
     } while (0)
     EC_SET_DIRECTION();
@@ -902,7 +902,8 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       if (__builtin_expect(go != 0, 1)) {
         {
           const uint64_t sb = (uint64_t)__double_as_longlong(best_s);
-          const uint32_t tag = ((uint32_t)EV_LIFT << 29) | (wgid & ~kFrozenBit);
+          // (the disk of a plain lift is not frozen: its id has no flag bit)
+          const uint32_t tag = ((uint32_t)EV_LIFT << 29) | wgid;
           writelane3(rec_lo, rec_hi, rec_tag, (uint32_t)sb, (uint32_t)(sb >> 32), tag, n_ring);
         }
         {
