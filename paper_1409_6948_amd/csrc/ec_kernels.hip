@@ -781,8 +781,9 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       // Plain lifts run in this inner loop, where the direction and its
       // derived constants do not change: the general path, which can change
       // them, sits outside it, so the common event needs no register copies
-      // where the two paths would otherwise join.  One exit, on a uniform
-      // integer (go: 1 after a plain lift while no poll has stopped).
+      // where the two paths would otherwise join.  The loop leaves on a
+      // uniform integer, tested after every event (go: 1 after a plain lift
+      // while no poll has stopped).
       int go = 1;
       // distances to the walls of the cell ahead: (wall - v) / d with 1/d
       // precomputed, clamped at 0
@@ -824,8 +825,10 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         valid = false;
         if (survivor) valid = contact(p.x - ax, p.y - ay, dx, dy, sig2, s);
       }
-      // The plain-lift test (below) of every lane's own candidate, made
-      // while the wave minimum is formed; the winning lane's result is read.
+      // The plain-lift test (the conditions are listed where its result is
+      // read) made by every lane on its own candidate while the wave minimum
+      // forms, so that it fills the DPP hazard slots; only the winning lane's
+      // result is used, computed with the winner's own values.
       int plain_l;
       {
         const double nxl = fma(s, dx, ax), nyl = fma(s, dy, ay);
@@ -879,12 +882,13 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         packed = uniform_i32(bx_ | (by_ << 8) | (kd << 16) | ((en ? 1 : 0) << 20) | \
                              ((ok_ ? 1 : 0) << 21) | (cr_ << 22));                  \
       } while (0)
-      // The common event, tested directly on the nearest disk: a disk (not
-      // frozen) is hit before either wall (a wall wins only when strictly
-      // nearer), chain length is left over, the window vouches for the move
-      // and the moved centre stays in its bin.  This is exactly the full
-      // decision (EC_DECIDE) finding such a lift; the general path makes the
-      // full decision for every other event.
+      // The common event, a plain lift: the nearest disk (not frozen) is hit
+      // before either wall (a wall wins only when strictly nearer), chain
+      // length is left over, the window vouches for the move and the moved
+      // centre stays in its bin.  This is exactly the full decision
+      // (EC_DECIDE) finding such a lift; the general path makes the full
+      // decision for every other event.  All but the walls come from the
+      // winning lane's test above.
       nax = fma(best_s, dx, ax);
       nay = fma(best_s, dy, ay);
       {
