@@ -114,6 +114,8 @@ def test_walled_scan_search(P):
     (4096, 0.30, 8, 20.0, 3),     # dilute: long flights, the window guard falls back often
     (2304, 0.65, 6, 12.0, 3),     # 3 x 3 blocks per colour, ragged
     (4096, 0.70, 4, 20.0, 2),     # large cells (17 sigma)
+    (576, 0.70, 8, 5.0, 3),       # 3 bins per cell side: all but the middle bin border a wall
+    (1024, 0.70, 8, 5.0, 3),      # 4 bins per cell side
 ])
 def test_walled_cells(P, n, eta, cells, ell, sweeps):
     _compare_full(P, n, eta, ell, cells, 1, sweeps, seed=7)
@@ -178,6 +180,7 @@ def test_dependency_wait_limit(P):
     (4096, 0.30, 8, 3.0, 2, 0),           # dilute: long flights, full-cell searches
     (2304, 0.65, 6, 2.0, 2, 2),           # one launch per phase
     (1024, 0.30, 4, 100.0, 2, 0),         # every chain longer than the cell: all undone
+    (576, 0.70, 8, 1.0, 3, 0),            # 3 bins per cell side
 ])
 def test_rejection_variant(P, n, eta, cells, ell, sweeps, flags):
     """Rejection at the cell boundary against the oracle bit for bit."""
