@@ -311,6 +311,7 @@ def test_full_size_first_phase_cells(P, name):
     (4096, 0.72, 8, 20.0, 3),
     (4096, 0.30, 8, 20.0, 3),
     (2304, 0.65, 6, 12.0, 2),
+    (576, 0.70, 8, 5.0, 3),       # 3 bins per cell side
 ])
 def test_fp32_screen_matches_oracle(P, n, eta, cells, ell, sweeps):
     _compare_full(P, n, eta, ell, cells, 1, sweeps, precision=1)
