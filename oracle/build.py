@@ -1,7 +1,8 @@
 """Build the CPU oracle shared library (test infrastructure only).
 
 The oracle is plain C compiled with -ffp-contract=off so that every fused
-multiply-add in it is an explicit fma() call.
+multiply-add in it is an explicit fma() call; -fopenmp for its optional
+phase-parallel mode (same results as the serial run).
 """
 import os
 import subprocess
@@ -14,7 +15,7 @@ LIB = os.path.join(HERE, "libec_oracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-fno-fast-math", "-fopenmp", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -202,6 +202,8 @@ void orc_direction(const orc_params* p, int64_t sweep, int32_t cell, int64_t cha
 /* ------------------------------------------------------------------------ */
 static orc_event* g_log = NULL;
 static int64_t g_log_cap = 0, g_log_n = 0, g_chain_no = 0;
+/* threads of the phase-parallel mode (1: serial) */
+static int g_threads = 1;
 
 void orc_set_log(orc_event* buf, int64_t capacity) {
   g_log = buf; g_log_cap = capacity; g_log_n = 0; g_chain_no = 0;
@@ -437,7 +439,13 @@ static void run_chain(chain_ctx* cx, int64_t a, double dx, double dy, double ell
 /* Start lists (step 5 of the PEC sweep)                                     */
 /* ------------------------------------------------------------------------ */
 /* Fill starts[0..n_m) with indices into the cell's id-ordered own list. */
-static void make_start_list(const orc_params* p, int64_t sweep, int32_t cell, int64_t n_c,
+static void make_start_list_(const orc_params* p, int64_t sweep, int32_t cell, int64_t n_c,
+                             int64_t n_m, int64_t* starts);
+void orc_start_list(const orc_params* p, int64_t sweep, int32_t cell, int64_t n_c, int64_t n_m,
+                    int64_t* starts) {
+  make_start_list_(p, sweep, cell, n_c, n_m, starts);
+}
+static void make_start_list_(const orc_params* p, int64_t sweep, int32_t cell, int64_t n_c,
                             int64_t n_m, int64_t* starts) {
   if (p->start_mode == ORC_START_DISTINCT) {
     /* shuffled list of distinct disks (the variant shown to be incorrect) */
@@ -495,7 +503,7 @@ static void sweep_periodic(const orc_params* p, double* x, double* y, int64_t sw
   cx.n_events = 0;
   int64_t n_m = p->chains_per_cell > 0 ? p->chains_per_cell : p->n;
   int64_t* starts = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_m > 0 ? n_m : 1));
-  make_start_list(p, sweep, 0, p->n, n_m, starts);
+  make_start_list_(p, sweep, 0, p->n, n_m, starts);
   for (int64_t k = 0; k < n_m; ++k) {
     double dx, dy;
     orc_direction(p, sweep, 0, k, &dx, &dy);
@@ -540,10 +548,13 @@ int orc_assign_cells(const orc_params* p, const double* x, const double* y, int6
 }
 
 /* Process one simulation cell of a sweep: stage own and frozen disks, run its
- * chains, write the moved disks back. */
+ * chains, write the moved disks back.  start/ids are the id-ordered own lists
+ * of all cells (cell c: ids[start[c] .. start[c+1])). */
 static void run_cell(const orc_params* p, double* x, double* y, int64_t sweep, int32_t cell,
-                     const int32_t* cell_of, const int64_t* own_ids, int64_t n_c, double sx,
-                     double sy, double* acc_delta, uint64_t* acc_cnt, uint64_t* cell_digest) {
+                     const int64_t* start, const int64_t* ids, double sx, double sy,
+                     double* acc_delta, uint64_t* acc_cnt, uint64_t* cell_digest) {
+  const int64_t* own_ids = &ids[start[cell]];
+  const int64_t n_c = start[cell + 1] - start[cell];
   int32_t C = p->cells;
   double L = orc_box_length(p->n, p->sigma, p->eta);
   double half_L = 0.5 * L;
@@ -561,13 +572,20 @@ static void run_cell(const orc_params* p, double* x, double* y, int64_t sweep, i
     vx[k] = vx0[k] = local_coord(x[i], sx, ox, L, half_L);
     vy[k] = vy0[k] = local_coord(y[i], sy, oy, L, half_L);
   }
-  /* frozen disks: centres of other cells within sigma of this cell (square band) */
+  /* frozen disks: centres of other cells within sigma of this cell (square
+   * band).  The cell side exceeds sigma, so every such centre lies in one of
+   * the eight neighbouring cells (C >= 4 makes them distinct); only their
+   * lists are read, which no cell of the same colour writes. */
   int64_t n_h = 0, cap_h = 64;
   double* hx = (double*)malloc(sizeof(double) * (size_t)cap_h);
   double* hy = (double*)malloc(sizeof(double) * (size_t)cap_h);
   int64_t* hg = (int64_t*)malloc(sizeof(int64_t) * (size_t)cap_h);
-  for (int64_t i = 0; i < p->n; ++i) {
-    if (cell_of[i] == cell) continue;
+  for (int32_t nbh = 0; nbh < 9; ++nbh) {
+   if (nbh == 4) continue;
+   const int32_t ncx = (cxi + nbh % 3 - 1 + C) % C, ncy = (cyi + nbh / 3 - 1 + C) % C;
+   const int32_t nc = ncy * C + ncx;
+   for (int64_t t = start[nc]; t < start[nc + 1]; ++t) {
+    const int64_t i = ids[t];
     double ux = local_coord(x[i], sx, ox, L, half_L);
     double uy = local_coord(y[i], sy, oy, L, half_L);
     if (ux >= -sigma && ux <= w + sigma && uy >= -sigma && uy <= w + sigma) {
@@ -579,6 +597,7 @@ static void run_cell(const orc_params* p, double* x, double* y, int64_t sweep, i
       }
       hx[n_h] = ux; hy[n_h] = uy; hg[n_h] = i; n_h++;
     }
+   }
   }
 
   chain_ctx cx;
@@ -598,7 +617,7 @@ static void run_cell(const orc_params* p, double* x, double* y, int64_t sweep, i
   int64_t n_m = 0;
   if (n_c > 0) n_m = p->chains_per_cell > 0 ? p->chains_per_cell : n_c;
   int64_t* starts = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_m > 0 ? n_m : 1));
-  make_start_list(p, sweep, cell, n_c, n_m, starts);
+  make_start_list_(p, sweep, cell, n_c, n_m, starts);
   for (int64_t k = 0; k < n_m; ++k) {
     double dx, dy;
     orc_direction(p, sweep, cell, k, &dx, &dy);
@@ -647,26 +666,40 @@ static void sweep_cells(const orc_params* p, double* x, double* y, int64_t sweep
   int64_t* start = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ncells + 1));
   int64_t* ids = (int64_t*)malloc(sizeof(int64_t) * (size_t)p->n);
   build_lists(cell_of, p->n, ncells, start, ids);
-  uint64_t total = 0;
+  /* the cells of one colour share nothing (each writes only its own disks and
+   * its own accumulators, and reads the lists of neighbours of other
+   * colours), so with threads they run in parallel; the sweep digest is a sum
+   * over cells and does not depend on their order */
+  uint64_t* h = (uint64_t*)calloc((size_t)ncells, sizeof(uint64_t));
+  int32_t* todo = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ncells > 0 ? ncells : 1));
+  const int threads = (g_log == NULL && g_threads > 1) ? g_threads : 1;
   for (int32_t q = 0; q < n_phases; ++q) {
     int colour = perm[q];
+    int32_t n_todo = 0;
     for (int32_t c = 0; c < ncells; ++c) {
       if (cell_colour(c, C) != colour) continue;
-      int32_t slot = -1;
       if (only) {
+        int32_t slot = -1;
         for (int32_t t = 0; t < n_only; ++t) if (only[t] == c) { slot = t; break; }
         if (slot < 0) continue;
       }
-      uint64_t h = 0;
-      run_cell(p, x, y, sweep, c, cell_of, &ids[start[c]], start[c + 1] - start[c], sx, sy,
-               acc_delta, acc_cnt, &h);
-      total += h * (2ULL * (uint64_t)c + 1ULL);
-      if (only_digest && slot >= 0) only_digest[slot] = h;
+      todo[n_todo++] = c;
     }
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads) if (threads > 1)
+    for (int32_t t = 0; t < n_todo; ++t)
+      run_cell(p, x, y, sweep, todo[t], start, ids, sx, sy, acc_delta, acc_cnt, &h[todo[t]]);
   }
+  uint64_t total = 0;
+  for (int32_t c = 0; c < ncells; ++c) total += h[c] * (2ULL * (uint64_t)c + 1ULL);
+  if (only_digest)
+    for (int32_t t = 0; t < n_only; ++t)
+      only_digest[t] = (only[t] >= 0 && only[t] < ncells) ? h[only[t]] : 0;
   if (digest_out) *digest_out = total;
+  free(h); free(todo);
   free(cell_of); free(start); free(ids);
 }
+
+void orc_set_threads(int32_t n) { g_threads = n > 1 ? n : 1; }
 
 int orc_run(const orc_params* p, double* x, double* y, int64_t sweep0, int64_t n_sweeps,
             double* acc_delta, uint64_t* acc_cnt, uint64_t* digests) {
@@ -690,6 +723,96 @@ int orc_run_cells(const orc_params* p, double* x, double* y, int64_t sweep, int3
   for (int32_t t = 0; t < n_cells; ++t) cell_digest[t] = 0;
   sweep_cells(p, x, y, sweep, n_phases, cells, n_cells, acc_delta, acc_cnt, NULL, cell_digest);
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One walled cell on its own (for exact stationarity checks)               */
+/* ------------------------------------------------------------------------ */
+int orc_cell_chains(const orc_params* p, double w, int64_t n_own, double* ox, double* oy,
+                    int64_t n_frozen, const double* fx, const double* fy, int64_t n_chains,
+                    double* trace, double* acc_delta, uint64_t* acc_cnt) {
+  if (!(w > 0.0) || n_own < 1 || n_frozen < 0 || n_chains < 0 || !(p->ell > 0.0) ||
+      !(p->sigma > 0.0) || p->boundary > ORC_BOUNDARY_REJECT)
+    return -1;
+  int64_t* ogid = (int64_t*)malloc(sizeof(int64_t) * (size_t)n_own);
+  int64_t* hgid = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_frozen > 0 ? n_frozen : 1));
+  for (int64_t i = 0; i < n_own; ++i) ogid[i] = i;
+  for (int64_t i = 0; i < n_frozen; ++i) hgid[i] = n_own + i;
+  chain_ctx cx;
+  memset(&cx, 0, sizeof cx);
+  cx.periodic = 0;
+  cx.n = n_own + n_frozen;
+  cx.w = w;
+  cx.sigma = p->sigma;
+  cx.n_own = n_own; cx.ox = ox; cx.oy = oy; cx.ogid = ogid;
+  cx.n_halo = n_frozen; cx.hx = fx; cx.hy = fy; cx.hgid = hgid;
+  cx.cell = 0;
+  cx.acc_delta = acc_delta;
+  cx.acc_cnt = acc_cnt;
+  cx.reject = p->boundary == ORC_BOUNDARY_REJECT;
+  for (int64_t k = 0; k < n_chains; ++k) {
+    /* chain k: start drawn with replacement and an isotropic direction, from
+     * the streams of sweep k, cell 0, chain 0 */
+    const int64_t a = orc_start_index(p, k, 0, 0, n_own);
+    double dx, dy;
+    orc_direction(p, k, 0, 0, &dx, &dy);
+    run_chain(&cx, a, dx, dy, p->ell);
+    if (trace)
+      for (int64_t i = 0; i < n_own; ++i) {
+        trace[(k * n_own + i) * 2] = ox[i];
+        trace[(k * n_own + i) * 2 + 1] = oy[i];
+      }
+  }
+  free(ogid); free(hgid); free(cx.u_a); free(cx.u_x); free(cx.u_y);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Smallest pair distance (overlap check)                                   */
+/* ------------------------------------------------------------------------ */
+double orc_min_pair_distance(int64_t n, double L, const double* x, const double* y, double r_cut,
+                             int64_t* i_out, int64_t* j_out) {
+  /* grid of g x g squares of side L/g >= r_cut: pairs closer than r_cut lie in
+   * the same or neighbouring squares (minimum image) */
+  int64_t g = (int64_t)floor(L / r_cut);
+  if (g < 3) g = 1;
+  if (g > 65536) g = 65536;
+  const double side = L / (double)g, half = 0.5 * L;
+  int64_t* head = (int64_t*)malloc(sizeof(int64_t) * (size_t)(g * g));
+  int64_t* next = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t* sq = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  for (int64_t c = 0; c < g * g; ++c) head[c] = -1;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t cx = (int64_t)floor(x[i] / side), cy = (int64_t)floor(y[i] / side);
+    cx = ((cx % g) + g) % g;
+    cy = ((cy % g) + g) % g;
+    sq[i] = cy * g + cx;
+    next[i] = head[sq[i]];
+    head[sq[i]] = i;
+  }
+  double best2 = INFINITY;
+  int64_t bi = -1, bj = -1;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t cx = sq[i] % g, cy = sq[i] / g;
+    const int64_t reach = g == 1 ? 0 : 1;
+    for (int64_t oy = -reach; oy <= reach; ++oy)
+      for (int64_t ox = -reach; ox <= reach; ++ox) {
+        const int64_t c = (((cy + oy) % g + g) % g) * g + (((cx + ox) % g + g) % g);
+        for (int64_t j = head[c]; j >= 0; j = next[j]) {
+          if (j <= i) continue;
+          double dx = x[j] - x[i], dy = y[j] - y[i];
+          if (dx < -half) dx += L; else if (dx >= half) dx -= L;
+          if (dy < -half) dy += L; else if (dy >= half) dy -= L;
+          const double d2 = dx * dx + dy * dy;
+          if (d2 < best2) { best2 = d2; bi = i; bj = j; }
+        }
+      }
+  }
+  free(head); free(next); free(sq);
+  if (!(best2 < r_cut * r_cut)) { best2 = INFINITY; bi = -1; bj = -1; }
+  if (i_out) *i_out = bi;
+  if (j_out) *j_out = bj;
+  return sqrt(best2);
 }
 
 /* ------------------------------------------------------------------------ */

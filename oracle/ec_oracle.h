@@ -127,6 +127,42 @@ void     orc_psi6_box(int64_t n, double L, const double* x, const double* y, dou
 void     orc_pair_histogram(const orc_params* p, const double* x, const double* y, double r_max,
                             int32_t n_bins, uint64_t* counts, uint64_t* overlaps);
 
+/* The start list of step 5 of the sweep for one cell: starts[k], k < n_m, is
+ * the index (into the cell's id-ordered list of n_c disks) where chain k
+ * starts; drawn with replacement, or from a shuffled list of distinct disks. */
+void     orc_start_list(const orc_params* p, int64_t sweep, int32_t cell, int64_t n_c,
+                        int64_t n_m, int64_t* starts);
+
+/*
+ * One walled square cell [0, w]^2 on its own: n_own movable disks (ox, oy,
+ * updated in place; ids 0..n_own-1) and n_frozen frozen disks (fx, fy; ids
+ * n_own..).  Chain k (k < n_chains) starts at a disk drawn with replacement
+ * and runs along an isotropic direction (the streams of sweep k, cell 0,
+ * chain 0 of the seed in p) for p->ell, reflecting or rejected at the walls
+ * and frozen disks as p->boundary says -- the chains of one simulation cell
+ * of Sec. 3.4.  trace (may be NULL) receives the movable positions after
+ * every chain (n_chains * n_own * 2 doubles); acc_delta[1] and
+ * acc_cnt[ORC_CNT_NCOL] are added to.  Returns 0, or -1 for bad arguments.
+ */
+int      orc_cell_chains(const orc_params* p, double w, int64_t n_own, double* ox, double* oy,
+                         int64_t n_frozen, const double* fx, const double* fy, int64_t n_chains,
+                         double* trace, double* acc_delta, uint64_t* acc_cnt);
+
+/* Smallest pair distance (minimum image in a periodic L x L box) among the
+ * pairs closer than r_cut, and that pair (i_out < j_out; -1 and +inf when no
+ * pair is closer than r_cut).  A grid of squares of side >= r_cut. */
+double   orc_min_pair_distance(int64_t n, double L, const double* x, const double* y, double r_cut,
+                               int64_t* i_out, int64_t* j_out);
+
+/*
+ * Phase-parallel mode: the cells of one colour phase run on n OpenMP threads
+ * (n <= 1: serial, the default).  Cells of one colour share nothing, each
+ * cell's chains run in their own order, and the sweep digest is a sum over
+ * cells, so every result is bit-identical to the serial run.  Ignored while
+ * an event log is set.
+ */
+void     orc_set_threads(int32_t n);
+
 /* Event log: set a buffer before orc_run; events beyond capacity are counted but dropped. */
 void     orc_set_log(orc_event* buf, int64_t capacity);
 int64_t  orc_log_count(void);

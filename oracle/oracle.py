@@ -66,6 +66,13 @@ def lib():
         L.orc_psi6.argtypes = [pp, dp, dp, C.c_double, dp, dp, dp, dp]
         L.orc_psi6_box.argtypes = [C.c_int64, C.c_double, dp, dp, C.c_double, dp, dp, dp, dp]
         L.orc_pair_histogram.argtypes = [pp, dp, dp, C.c_double, C.c_int32, u64p, u64p]
+        L.orc_set_threads.argtypes = [C.c_int32]
+        L.orc_start_list.argtypes = [pp, C.c_int64, C.c_int32, C.c_int64, C.c_int64, i64p]
+        L.orc_cell_chains.restype = C.c_int
+        L.orc_cell_chains.argtypes = [pp, C.c_double, C.c_int64, dp, dp, C.c_int64, dp, dp,
+                                      C.c_int64, dp, dp, u64p]
+        L.orc_min_pair_distance.restype = C.c_double
+        L.orc_min_pair_distance.argtypes = [C.c_int64, C.c_double, dp, dp, C.c_double, i64p, i64p]
         L.orc_set_log.argtypes = [C.POINTER(Event), C.c_int64]
         L.orc_log_count.restype = C.c_int64
         _lib = L
@@ -80,6 +87,11 @@ def params(n, eta, ell, cells, dir_mode=DIR_ISO, seed=1, sigma=1.0, chains_per_c
            start_mode=START_REPLACE, system=0, boundary=BOUNDARY_REFLECT):
     return Params(int(n), float(sigma), float(eta), float(ell), int(cells), int(chains_per_cell),
                   int(dir_mode), int(start_mode), int(seed), int(system), int(boundary))
+
+
+def set_threads(n):
+    """Threads of the phase-parallel mode (1 = serial); results are identical."""
+    lib().orc_set_threads(int(n))
 
 
 def box_length(n, sigma, eta):
@@ -120,6 +132,46 @@ def direction(p, sweep, cell, chain):
 
 def collision_distance(rx, ry, dx, dy, sigma=1.0):
     return lib().orc_collision_distance(rx, ry, dx, dy, sigma)
+
+
+def start_list(p, sweep, cell, n_c, n_m):
+    """Start indices of the n_m chains of a cell with n_c disks (step 5)."""
+    out = np.zeros(max(int(n_m), 1), dtype=np.int64)
+    lib().orc_start_list(C.byref(p), int(sweep), int(cell), int(n_c), int(n_m), _ptr(out, C.c_int64))
+    return out[:int(n_m)]
+
+
+def cell_chains(p, w, own_x, own_y, frozen_x=(), frozen_y=(), n_chains=1, trace=True):
+    """Chains of one walled cell [0, w]^2 (see orc_cell_chains): returns the
+    final positions, the trace (n_chains, n_own, 2) or None, the contact sum
+    and the counts."""
+    ox = np.ascontiguousarray(own_x, dtype=np.float64).copy()
+    oy = np.ascontiguousarray(own_y, dtype=np.float64).copy()
+    fx = np.ascontiguousarray(frozen_x, dtype=np.float64)
+    fy = np.ascontiguousarray(frozen_y, dtype=np.float64)
+    n_own, n_fr = len(ox), len(fx)
+    tr = np.zeros((int(n_chains), n_own, 2)) if trace else None
+    acc = np.zeros(1)
+    cnt = np.zeros(CNT_NCOL, dtype=np.uint64)
+    dp = C.POINTER(C.c_double)
+    rc = lib().orc_cell_chains(C.byref(p), float(w), n_own, _ptr(ox, C.c_double), _ptr(oy, C.c_double),
+                               n_fr, fx.ctypes.data_as(dp) if n_fr else None,
+                               fy.ctypes.data_as(dp) if n_fr else None, int(n_chains),
+                               tr.ctypes.data_as(dp) if trace else None, _ptr(acc, C.c_double),
+                               _ptr(cnt, C.c_uint64))
+    if rc != 0:
+        raise ValueError("invalid arguments")
+    return ox, oy, tr, float(acc[0]), cnt
+
+
+def min_pair_distance(x, y, L, r_cut=1.0):
+    """(smallest minimum-image pair distance below r_cut or inf, i, j)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    i, j = C.c_int64(), C.c_int64()
+    d = lib().orc_min_pair_distance(len(x), float(L), _ptr(x, C.c_double), _ptr(y, C.c_double),
+                                    float(r_cut), C.byref(i), C.byref(j))
+    return d, i.value, j.value
 
 
 def assign_cells(p, x, y, sweep):

@@ -1,0 +1,151 @@
+"""Parity of the full-size workloads with the CPU oracle, across all four
+colour phases and across sweeps.
+
+A cell of colour phase q reads the disks that its eight neighbours of
+earlier phases have just moved (Sec. 3.4, steps 4-6).  The oracle replays a
+sample of cells of every phase together with their dependency cones (the
+earlier-phase neighbours, recursively) from the positions at the start of the
+sweep, which reproduces those cells exactly; positions, per-cell tallies and
+per-cell event digests must then equal the device's bit for bit.  Sweep 1 is
+replayed from the device's positions and tallies after sweep 0.  The 65k
+workload is compared whole, every cell, over three sweeps.  Every
+configuration is checked for overlaps with the oracle's pair search.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests import cones, inputs
+
+pytestmark = pytest.mark.gpu
+
+# worker threads of the oracle's phase-parallel mode (bit-identical to serial)
+THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1409_6948_amd as P
+    P.load_library()
+    return P
+
+
+def _gpu_state(g):
+    x, y = g.get_positions()
+    delta, cnt = g.get_cell_tallies()
+    return x, y, delta, cnt, g.get_cell_digests()
+
+
+def _sample_targets(C, perm, per_phase, seed):
+    """per_phase cells of every colour phase (the first and last of the phase,
+    the rest drawn with a seeded generator)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(4):
+        cells = [c for c in range(C * C) if cones.phase_of_cell(C, perm, c) == q]
+        pick = {cells[0], cells[-1]}
+        pick |= set(int(v) for v in rng.choice(cells, size=per_phase - 2, replace=False))
+        out.extend(sorted(pick))
+    return out
+
+
+def _replay_and_compare(p, sweep, start_xy, start_tallies, after, targets):
+    """Replay the union of the targets' cones of `sweep` on the oracle from
+    start_xy (and the per-cell tallies before the sweep) and compare every
+    replayed cell with the device state `after` the sweep."""
+    C = p.cells
+    perm = O.sweep_draws(p, sweep)[2]
+    union = set()
+    for c in targets:
+        union |= cones.dependency_cone(C, perm, c)
+    cells = sorted(union)
+    st = O.State(p, start_xy[0], start_xy[1])
+    st.acc_delta[:] = start_tallies[0]
+    st.acc_cnt[:] = start_tallies[1]
+    O.set_threads(THREADS)
+    try:
+        dig = st.run_cells(sweep, cells, n_phases=4)
+    finally:
+        O.set_threads(1)
+    gx, gy, gdelta, gcnt, gdig = after
+    cell_of = O.assign_cells(p, start_xy[0], start_xy[1], sweep)
+    mask = np.isin(cell_of, cells)
+    assert mask.sum() > 100 * len(cells)
+    np.testing.assert_array_equal(gx[mask], st.x[mask])
+    np.testing.assert_array_equal(gy[mask], st.y[mask])
+    for t, c in enumerate(cells):
+        assert gdelta[c] == st.acc_delta[c], f"cell {c}"
+        np.testing.assert_array_equal(gcnt[c], st.acc_cnt[c], err_msg=f"cell {c}")
+        assert gdig[c] == dig[t], f"cell {c} digest"
+    phases = sorted({cones.phase_of_cell(C, perm, c) for c in targets})
+    assert phases == [0, 1, 2, 3]
+    return len(cells)
+
+
+@pytest.mark.parametrize("name", ["pec_1m", "pec_16m"])
+def test_full_size_cones_of_every_phase_two_sweeps(P, name):
+    w = inputs.WORKLOADS[name]
+    n, eta, C, ell = w["n"], w["eta"], w["cells"], w["ell"]
+    _say(f"[full-size] {name}: n={n} eta={eta} C={C} ell={ell}: two GPU sweeps")
+    g = P.System(P.make_params(n, eta, ell, C, seed=w["seed"]))
+    g.sweep(1)
+    s1 = _gpu_state(g)
+    g.sweep(1)
+    s2 = _gpu_state(g)
+    g.close()
+    p = O.params(n, eta, ell, C, dir_mode=O.DIR_ISO, seed=w["seed"])
+    x0, y0 = O.lattice(p)
+    nc = C * C
+    zero = (np.zeros(nc), np.zeros((nc, O.CNT_NCOL), dtype=np.uint64))
+    for sweep, start, tallies, after in ((0, (x0, y0), zero, s1), (1, s1[:2], (s1[2], s1[3]), s2)):
+        targets = _sample_targets(C, O.sweep_draws(p, sweep)[2], 4, seed=sweep)
+        _say(f"[full-size] {name}: sweep {sweep}: oracle replay of 4 cells per phase and their cones")
+        k = _replay_and_compare(p, sweep, start, tallies, after, targets)
+        _say(f"[full-size] {name}: sweep {sweep}: {k} cells equal")
+    # one chain per disk per sweep, and no overlap anywhere
+    assert int(s2[3][:, O.CNT_CHAINS].sum()) == 2 * n
+    _say(f"[full-size] {name}: overlap check of all {n} disks")
+    L = O.box_length(n, 1.0, eta)
+    for xy in (s1[:2], s2[:2]):
+        d, i, j = O.min_pair_distance(xy[0], xy[1], L, r_cut=1.0 - 1e-12)
+        assert d == np.inf, (d, i, j)
+
+
+def test_pec_65k_three_whole_sweeps(P):
+    """N = 65,536, eta = 0.70, 16 x 16 cells, ell = 20 sigma from the lattice:
+    every cell of three sweeps against the oracle (positions, per-sweep
+    digests, per-cell tallies)."""
+    w = inputs.WORKLOADS["pec_65k"]
+    n, eta, C, ell = w["n"], w["eta"], w["cells"], w["ell"]
+    sweeps = 3
+    _say(f"[full-size] pec_65k: {sweeps} whole sweeps")
+    g = P.System(P.make_params(n, eta, ell, C, seed=w["seed"]))
+    g.sweep(sweeps)
+    gx, gy = g.get_positions()
+    delta, cnt = g.get_cell_tallies()
+    dig = g.get_digests(sweeps)
+    p = O.params(n, eta, ell, C, dir_mode=O.DIR_ISO, seed=w["seed"])
+    st = O.State(p)
+    O.set_threads(THREADS)
+    try:
+        st.run(sweeps)
+    finally:
+        O.set_threads(1)
+    np.testing.assert_array_equal(dig, np.array(st.digests, dtype=np.uint64))
+    np.testing.assert_array_equal(gx, st.x)
+    np.testing.assert_array_equal(gy, st.y)
+    np.testing.assert_array_equal(delta, st.acc_delta)
+    np.testing.assert_array_equal(cnt, st.acc_cnt)
+    d, _, _ = O.min_pair_distance(gx, gy, O.box_length(n, 1.0, eta), r_cut=1.0 - 1e-12)
+    assert d == np.inf

@@ -3,9 +3,8 @@
 Positions are compared bit for bit, and so are the event digests, the
 per-cell pressure sums and the event counts: both sides follow the same
 arithmetic and random-number contract, so the trajectories are identical.
-Small systems are compared over whole runs; the full-size workloads are
-compared on a sample of first-phase cells, which only see positions from the
-start of the sweep and so can be replayed by the oracle one by one.
+Small systems are compared over whole runs here; the full-size workloads are
+compared in test_gpu_full_size.py.
 """
 import math
 import sys
@@ -235,73 +234,6 @@ def test_set_positions_rejects_overlap(P):
     small = np.zeros(3)
     ptr = small.ctypes.data_as(E.C.POINTER(E.C.c_double))
     assert E.load_library().ec_get_positions(g.h, ptr, ptr, 3) == E.EC_E_INVALID
-
-
-def _min_distance_grid(x, y, L):
-    """Smallest pair distance (minimum image) with a grid of side >= 1."""
-    g = int(L // 1.0)
-    cx = np.minimum((x / (L / g)).astype(np.int64), g - 1)
-    cy = np.minimum((y / (L / g)).astype(np.int64), g - 1)
-    order = np.lexsort((cx, cy))
-    key = cy[order] * g + cx[order]
-    starts = np.searchsorted(key, np.arange(g * g))
-    ends = np.searchsorted(key, np.arange(g * g), side="right")
-    best = np.inf
-    xs, ys = x[order], y[order]
-    for oy in (-1, 0, 1):
-        for ox in (-1, 0, 1):
-            nb = ((cy[order] + oy) % g) * g + (cx[order] + ox) % g
-            cnt = ends[nb] - starts[nb]
-            for k in range(int(cnt.max())):
-                has = cnt > k
-                j = starts[nb[has]] + k
-                i = np.nonzero(has)[0]
-                keep = j != i
-                i, j = i[keep], j[keep]
-                dx = xs[j] - xs[i]
-                dy = ys[j] - ys[i]
-                dx -= L * np.round(dx / L)
-                dy -= L * np.round(dy / L)
-                if len(dx):
-                    best = min(best, float(np.sqrt((dx * dx + dy * dy).min())))
-    return best
-
-
-@pytest.mark.parametrize("name", ["pec_65k", "pec_1m", "pec_16m"])
-def test_full_size_first_phase_cells(P, name):
-    """Full-size workload, one sweep on the GPU from the lattice; a sample of
-    first-phase cells replayed by the oracle must match bit for bit, and the
-    whole configuration must stay overlap-free."""
-    w = inputs.WORKLOADS[name]
-    n, eta, C, ell = w["n"], w["eta"], w["cells"], w["ell"]
-    _say(f"[full-size] {name}: n={n} eta={eta} C={C} ell={ell}: one GPU sweep")
-    g = _gpu_system(P, n, eta, ell, C, 1, seed=w["seed"])
-    g.sweep(1)
-    gx, gy = g.get_positions()
-    delta, cnt = g.get_cell_tallies()
-    cdig = g.get_cell_digests()
-    _say(f"[full-size] {name}: oracle replay of sampled first-phase cells")
-    p = O.params(n, eta, ell, C, dir_mode=O.DIR_ISO, seed=w["seed"])
-    st = O.State(p)
-    _, _, perm = O.sweep_draws(p, 0)
-    first = [c for c in range(C * C) if ((c % C) & 1) | (((c // C) & 1) << 1) == perm[0]]
-    rng = np.random.default_rng(0)
-    sample = sorted(set([first[0], first[-1]] + list(rng.choice(first, size=4, replace=False))))
-    cell_of = O.assign_cells(p, st.x, st.y, 0)
-    dig = st.run_cells(0, sample, n_phases=1)
-    mask = np.isin(cell_of, sample)
-    assert mask.sum() > 200
-    np.testing.assert_array_equal(gx[mask], st.x[mask])
-    np.testing.assert_array_equal(gy[mask], st.y[mask])
-    for t, c in enumerate(sample):
-        assert delta[c] == st.acc_delta[c]
-        np.testing.assert_array_equal(cnt[c], st.acc_cnt[c])
-        assert cdig[c] == dig[t]
-    assert int(cnt[:, O.CNT_CHAINS].sum()) == n  # one chain per disk per sweep
-    L = O.box_length(n, 1.0, eta)
-    if n <= 1 << 20:
-        _say(f"[full-size] {name}: overlap check")
-        assert _min_distance_grid(gx, gy, L) > 1.0 - 1e-12
 
 
 # ---------------------------------------------------------------------------

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from tests import inputs
+from tests import cones, inputs
 
 SIG = 1.0
 
@@ -803,3 +803,204 @@ def test_mean_free_path_at_eta_071_matches_the_paper():
     d = st.acc_cnt.sum(axis=0).astype(float) - c0
     lam = p.ell * d[O.CNT_CHAINS] / (d[O.CNT_LIFTS] + d[O.CNT_FROZEN])
     assert abs(lam - gold["lambda0_over_sigma"]) <= 0.005, lam
+
+
+# --------------------------------------------------------------------------
+# Phase-parallel oracle mode (same bits as the serial run)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,eta,cells,ell,sweeps,kw", [
+    (4096, 0.72, 8, 20.0, 2, {}),
+    (2304, 0.65, 6, 12.0, 2, {}),
+    (1024, 0.60, 4, 5.0, 3, dict(chains_per_cell=50, start_mode=O.START_DISTINCT)),
+    (1024, 0.55, 4, 1.0, 3, dict(boundary=O.BOUNDARY_REJECT)),
+])
+def test_phase_parallel_equals_serial(n, eta, cells, ell, sweeps, kw):
+    """Cells of one colour share nothing (Sec. 3.4, step 4), so running them on
+    several threads must give every bit of the serial run."""
+    p = O.params(n, eta, ell, cells, **kw)
+    out = []
+    for threads in (1, 4):
+        O.set_threads(threads)
+        try:
+            st = O.State(p)
+            st.run(sweeps)
+        finally:
+            O.set_threads(1)
+        out.append(st)
+    a, b = out
+    np.testing.assert_array_equal(a.x, b.x)
+    np.testing.assert_array_equal(a.y, b.y)
+    np.testing.assert_array_equal(a.acc_delta, b.acc_delta)
+    np.testing.assert_array_equal(a.acc_cnt, b.acc_cnt)
+    assert a.digests == b.digests
+
+
+# --------------------------------------------------------------------------
+# Start lists: index mapping and the distinct-start shuffle
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("bits", [1, 3, 8, 20])
+def test_start_index_power_of_two_is_top_bits(bits):
+    """For n = 2^b the multiply-shift index map never rejects and returns the
+    top b bits of the first Philox word of the stream (key (seed, 2),
+    counter (sweep, cell, chain, 0)), taken from numpy's generator."""
+    p = O.params(4096, 0.7, 1.0, 8, seed=9)
+    n = 1 << bits
+    for sweep, cell, chain in [(0, 0, 0), (3, 5, 7), (11, 63, 1000), (2, 17, 99)]:
+        word = _numpy_philox_block([sweep, cell, chain, 0], [9, 2])[0]
+        assert O.start_index(p, sweep, cell, chain, n) == word >> (64 - bits)
+
+
+def test_distinct_start_shuffle_uniform_over_permutations():
+    """The distinct-start control (Fig. 2-3) uses a shuffled list of the cell's
+    disks: for a cell of 4 disks every one of the 24 orders must be equally
+    likely (an off-by-one shuffle reaches only some of them, or not evenly)."""
+    import itertools
+    p = O.params(4096, 0.7, 1.0, 8, start_mode=O.START_DISTINCT, seed=5)
+    perms = {q: i for i, q in enumerate(itertools.permutations(range(4)))}
+    counts = np.zeros(24)
+    draws = 24 * 500
+    for s in range(draws):
+        lst = tuple(int(v) for v in O.start_list(p, s, 3, 4, 4))
+        counts[perms[lst]] += 1  # KeyError if not a permutation of 0..3
+    e = draws / 24
+    chi2 = ((counts - e) ** 2 / e).sum()
+    assert counts.min() > 0
+    assert chi2 < 55.0  # 23 dof, P ~ 2e-4
+    # with n_m > n_c the list repeats: chain k starts at list[k mod n_c]
+    lst = O.start_list(p, 7, 3, 4, 10)
+    np.testing.assert_array_equal(lst[4:8], lst[:4])
+    np.testing.assert_array_equal(lst[8:], lst[:2])
+
+
+def test_replacement_start_list_uses_independent_draws():
+    """With replacement (Fig. 2) chain k's start is the index draw of stream k."""
+    p = O.params(4096, 0.7, 1.0, 8, seed=5)
+    lst = O.start_list(p, 2, 9, 37, 50)
+    assert [int(v) for v in lst] == [O.start_index(p, 2, 9, k, 37) for k in range(50)]
+
+
+# --------------------------------------------------------------------------
+# Exact stationary laws of one walled cell (Sec. 3.4, Fig. 1 right)
+# --------------------------------------------------------------------------
+def _bin_mass(w, nb, weight, res=1500):
+    """Integral of weight(X, Y) over each of nb x nb bins of [0, w]^2 (midpoint
+    rule on res x res points per bin), normalised to total 1."""
+    h = w / nb
+    t = (np.arange(res) + 0.5) / res * h
+    P = np.zeros((nb, nb))
+    for i in range(nb):
+        for j in range(nb):
+            X, Y = np.meshgrid(i * h + t, j * h + t, indexing="ij")
+            P[i, j] = weight(X, Y).mean()
+    return P / P.sum()
+
+
+def _batch_z(samples, hist, P, batches=50):
+    """z-scores of the bin frequencies against P, with batch-means errors (the
+    chain samples are correlated); bins with P = 0 must stay empty."""
+    m = len(samples) // batches
+    f = np.array([hist(samples[b * m:(b + 1) * m]) for b in range(batches)])
+    mean = f.mean(0)
+    se = f.std(0, ddof=1) / math.sqrt(batches)
+    assert np.all(mean[P == 0] == 0)
+    k = P > 0
+    return (mean[k] - P[k]) / se[k]
+
+
+def test_one_disk_beside_a_frozen_disk_is_uniform():
+    """One movable disk in a walled cell [0, 3]^2 next to one frozen disk (in
+    the band left of the cell): chains reflect at the walls and, with equal
+    angles, at the frozen disk.  The stationary law is uniform over the cell
+    minus the disk of radius sigma around the frozen centre (the billiard flow
+    keeps the uniform measure; each chain restarts with a uniform direction)."""
+    w, nb, F = 3.0, 6, (-0.4, 1.3)
+    p = O.params(1, 0.5, 7.0, 4, seed=11)
+    _, _, tr, _, cnt = O.cell_chains(p, w, [2.0], [1.5], [F[0]], [F[1]], n_chains=200000)
+    assert cnt[O.CNT_FROZEN] > 50000 and cnt[O.CNT_WALLS] > 200000
+    assert np.all((tr[:, 0, 0] - F[0]) ** 2 + (tr[:, 0, 1] - F[1]) ** 2 >= 1.0 - 1e-12)
+    P = _bin_mass(w, nb, lambda X, Y: ((X - F[0]) ** 2 + (Y - F[1]) ** 2 >= 1.0).astype(float))
+
+    def hist(s):
+        H, _, _ = np.histogram2d(s[:, 0, 0], s[:, 0, 1], bins=nb, range=[[0, w], [0, w]])
+        return H / len(s)
+
+    z = _batch_z(tr, hist, P)
+    # about 33 bins; batch-means z are t-distributed with 49 dof
+    assert np.abs(z).max() < 4.5
+    assert (z ** 2).sum() < len(z) + 5.0 * math.sqrt(2 * len(z)) + 10.0
+
+
+def test_two_disks_in_a_walled_cell_separation_law():
+    """Two movable disks in a walled cell [0, 3]^2 with lifts between them and
+    reflections at the walls: the stationary law is uniform over the allowed
+    pairs, so the separation r = r1 - r2 has density proportional to
+    (w - |r_x|)(w - |r_y|) on |r| >= sigma."""
+    w, nb = 3.0, 6
+    p = O.params(2, 0.5, 7.0, 4, seed=12)
+    _, _, tr, _, cnt = O.cell_chains(p, w, [0.7, 2.2], [0.7, 2.2], n_chains=200000)
+    assert cnt[O.CNT_LIFTS] > 100000 and cnt[O.CNT_WALLS] > 200000
+    P = _bin_mass(w, nb, lambda X, Y: (w - X) * (w - Y) * (X * X + Y * Y >= 1.0))
+
+    def hist(s):
+        r = np.abs(s[:, 0, :] - s[:, 1, :])
+        H, _, _ = np.histogram2d(r[:, 0], r[:, 1], bins=nb, range=[[0, w], [0, w]])
+        return H / len(s)
+
+    z = _batch_z(tr, hist, P)
+    assert np.abs(z).max() < 4.5
+    assert (z ** 2).sum() < len(z) + 5.0 * math.sqrt(2 * len(z)) + 10.0
+
+
+# --------------------------------------------------------------------------
+# Overlap check used on the full-size workloads
+# --------------------------------------------------------------------------
+def test_min_pair_distance_against_brute_force():
+    rng = np.random.default_rng(3)
+    for n, L, rc in [(300, 20.0, 1.0), (50, 5.0, 1.0), (400, 30.0, 2.5), (2, 4.0, 1.9)]:
+        x = rng.uniform(0, L, n)
+        y = rng.uniform(0, L, n)
+        dx = x[None, :] - x[:, None]
+        dy = y[None, :] - y[:, None]
+        dx -= L * np.round(dx / L)
+        dy -= L * np.round(dy / L)
+        d = np.sqrt(dx * dx + dy * dy)
+        d[np.arange(n), np.arange(n)] = np.inf
+        ref = d.min()
+        got, i, j = O.min_pair_distance(x, y, L, rc)
+        if ref < rc:
+            assert abs(got - ref) <= 1e-12 * L and abs(d[i, j] - ref) <= 1e-12 * L
+        else:
+            assert got == math.inf and i == -1 and j == -1
+
+
+# --------------------------------------------------------------------------
+# Dependency cones: a cell of a later phase replayed from the sweep start
+# --------------------------------------------------------------------------
+def test_dependency_cone_replays_later_phases():
+    """A cell of colour phase q reads the disks its earlier-phase neighbours
+    have moved (Sec. 3.4, steps 4-6).  Running only the cells of its cone of
+    earlier-phase neighbours (recursively) from the sweep start must give the
+    cell exactly what the full sweep gives it."""
+    p = O.params(4096, 0.70, 10.0, 8, seed=4)
+    full = O.State(p)
+    full.run(2)
+    x0, y0 = O.lattice(p)
+    one = O.State(p)
+    one.run(1)
+    for sweep, (sx, sy) in ((0, (x0, y0)), (1, (one.x, one.y))):
+        for target in (9, 18, 27, 36, 45, 54):
+            cells = cones.dependency_cone(p.cells, O.sweep_draws(p, sweep)[2], target)
+            st = O.State(p, sx, sy)
+            if sweep == 1:
+                st.acc_delta[:] = one.acc_delta
+                st.acc_cnt[:] = one.acc_cnt
+            dig = st.run_cells(sweep, sorted(cells), n_phases=4)
+            ref = full if sweep == 1 else one
+            cell_of = O.assign_cells(p, sx, sy, sweep)
+            mask = np.isin(cell_of, sorted(cells))
+            np.testing.assert_array_equal(st.x[mask], ref.x[mask])
+            np.testing.assert_array_equal(st.y[mask], ref.y[mask])
+            for c in cells:
+                assert st.acc_delta[c] == ref.acc_delta[c]
+                np.testing.assert_array_equal(st.acc_cnt[c], ref.acc_cnt[c])
+            assert len(dig) == len(cells)
