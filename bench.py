@@ -48,11 +48,20 @@ from tests import inputs  # noqa: E402  (seeded workload definitions; no method 
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_PEAK_TF = 78.6     # MI355X FP64 vector, TFLOP/s
-# FP64 work of one event (algorithmic): contact tests of the disks in the
+# FP64 work of one lift (algorithmic): contact tests of the disks in the
 # 3 x 3 neighbourhood of sigma-sized squares (about 8 disks at rho sigma^2 =
 # 0.92; 2 sub, 2 mul + 2 fma for r.d and r x d, 1 fma, sqrt, sub = 12 flop
 # each) plus the commit (2 fma) = 8 * 12 + 4 = 100 flop.
-FLOP_PER_EVENT = 100.0
+FLOP_PER_LIFT = 100.0
+# HBM bytes per disk of the two rebin kernels (algorithmic): the count kernel
+# reads x, y and writes the cell index; the scatter kernel reads the cell
+# index and writes the id into its cell's list.
+COUNT_BYTES_PER_DISK = 16 + 4
+SCATTER_BYTES_PER_DISK = 4 + 4
+# simulation cells that can run at once on the chip: one wavefront per SIMD
+# (256 CUs x 4 SIMDs), and a 64 x 64 grid admits at most 1024 non-adjacent cells
+CONCURRENT_CELLS = 1024
+CLOCK_GHZ = 2.4
 # HBM bytes of one sweep per disk (algorithmic): rebin reads x, y (16) and
 # writes/reads the cell index (8) and the id list (8); the four phases read
 # every disk once as its own (16 + 4 id) and write it back (16), and read the
@@ -65,45 +74,88 @@ SCHEDULE_FLAGS = {"auto": lambda P: 0,
                   "phase-launches": lambda P: P.EC_FLAG_PHASE_LAUNCHES}
 
 
+def _kernel_source_sha():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1409_6948_amd", "csrc", "ec_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def _profile_line(name, key):
+    """key=value fields of the machine-readable line `key:` of a committed
+    profile summary, or None when the file is missing or was taken on another
+    kernel source."""
+    import re
+    prof = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(prof):
+        return None
+    sha = _kernel_source_sha()
+    for line in open(prof):
+        if line.startswith(key + ":"):
+            f = dict(re.findall(r"(\w+)=(\S+)", line))
+            if f.get("source_sha256_prefix") == sha:
+                return f
+    return None
+
+
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of the simulation-cell kernel from the committed
     counter summary, or None when the kernel source has changed since the
     counters were taken."""
-    import hashlib
-    import re
-    src = os.path.join(ROOT, "paper_1409_6948_amd", "csrc", "ec_kernels.hip")
-    prof = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
-    if not os.path.exists(prof):
+    f = _profile_line(f"{kernel}_{workload}_counters.md", "traffic")
+    if f is None:
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    for line in open(prof):
-        m = re.match(r"traffic: .*source_sha256_prefix=(\w+) read_bytes_per_launch=(\S+) "
-                     r"write_bytes_per_launch=(\S+)", line)
-        if m and m.group(1) == sha:
-            return float(m.group(2)) + float(m.group(3))
-    return None
+    return float(f["read_bytes_per_launch"]) + float(f["write_bytes_per_launch"])
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """Time the CPU oracle on first-phase cells of sweep 0 from the lattice."""
+def measured_cycles_per_event(kernel, workload):
+    """Wavefront cycles per event of the simulation-cell kernel from the
+    committed SQ counters (same kernel source), or None."""
+    f = _profile_line(f"{kernel}_{workload}_sq_counters.md", "tstep")
+    return None if f is None else float(f["cycles_per_event"])
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, threads=None):
+    """The oracle in its phase-parallel mode (the paper's own scheme: one
+    thread per simulation cell of the running colour, Sec. 3.4) on the host's
+    cores: one whole sweep of the workload from the lattice -- rebin, the four
+    colour phases, write-back -- or, above 4M disks, the first colour phase of
+    that sweep (a quarter of the cells)."""
     from oracle import oracle as O
+    from oracle import build as OB
+    threads = threads or max(1, min(16, os.cpu_count() or 1))
     p = O.params(w["n"], w["eta"], w["ell"], w["cells"], dir_mode=O.DIR_ISO, seed=w["seed"])
     st = O.State(p)
-    C = w["cells"]
-    _, _, perm = O.sweep_draws(p, 0)
-    first = [c for c in range(C * C) if ((c % C) & 1) | (((c // C) & 1) << 1) == perm[0]]
-    done, lifts, t_cells = 0, 0, 0.0
-    for c in first:
+    whole = w["n"] <= (1 << 22)
+    O.set_threads(threads)
+    try:
         t0 = time.perf_counter()
-        st.run_cells(0, [c], n_phases=1)
-        t_cells += time.perf_counter() - t0
-        done += 1
-        if t_cells >= budget_s:
-            break
+        if whole:
+            st.run(1)
+        else:
+            C = w["cells"]
+            perm = O.sweep_draws(p, 0)[2]
+            first = [c for c in range(C * C) if ((c % C) & 1) | (((c // C) & 1) << 1) == perm[0]]
+            st.run_cells(0, first, n_phases=1)
+        secs = time.perf_counter() - t0
+    finally:
+        O.set_threads(1)
     lifts = int(st.acc_cnt[:, O.CNT_LIFTS].sum())
-    return {"value": lifts / t_cells, "unit": "lifts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} first-phase cells of sweep 0 of {w['n']} disks from the lattice "
-                      f"({lifts} lifts in {t_cells:.1f} s; rebin and halo scan excluded)"}
+    what = "one whole sweep" if whole else "the first colour phase of sweep 0"
+    return {"value": lifts / secs, "unit": "lifts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{what} of {w['n']} disks from the lattice: {lifts} lifts in {secs:.1f} s, "
+                      f"rebin and staging included; phase-parallel oracle on {threads} threads",
+            "host": {"nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+                     "compiler": "gcc " + " ".join(OB.FLAGS)}}
 
 
 def main():
@@ -118,9 +170,10 @@ def main():
                          "dependencies, or one launch per phase; auto = the library's default "
                          "(one launch for a system alone, phase launches for a batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=("fp64", "fp32-screen"), default="fp64",
+    ap.add_argument("--precision", choices=("fp64", "fp32-screen"), default=None,
                     help="fp32-screen: FP32 screening of candidates, FP64 for the survivors "
-                         "and every commit (identical events)")
+                         "and every commit (identical events); default: the workload's own "
+                         "(FP64 for pec_1m, FP32 screen for pec_16m and batch64)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -149,7 +202,8 @@ def main():
         return bench_tau(args, torch, P)
     w = dict(inputs.WORKLOADS[args.workload])
     torch.cuda.set_device(0)
-    prec = P.EC_PREC_FP64 if args.precision == "fp64" else P.EC_PREC_FP32_SCREEN
+    precision = args.precision or w.get("precision", "fp64")
+    prec = P.EC_PREC_FP64 if precision == "fp64" else P.EC_PREC_FP32_SCREEN
     flags = SCHEDULE_FLAGS[args.schedule](P)
     kernel = "k_phase" if args.schedule == "phase-launches" else "k_sweep_cells"
     p = P.make_params(w["n"], w["eta"], w["ell"], w["cells"], dir_mode=w["dir_mode"],
@@ -165,37 +219,68 @@ def main():
         torch.cuda.synchronize()
         print(f"# copy probe: {nbytes} bytes read and written", file=sys.stderr, flush=True)
         del src, dst
-    print(f"# workload {args.workload}: warmup {args.warmup} sweeps", file=sys.stderr, flush=True)
+    print(f"# workload {args.workload} ({precision}): warmup {args.warmup} sweeps", file=sys.stderr,
+          flush=True)
     g.sweep(args.warmup)
     torch.cuda.synchronize()
     g.reset_tallies()
+    # the library records HIP events around its kernels on its own stream and
+    # reads them after the timed region: the sweeps run free, back to back
     g.set_timing(True)
     stream = g.stream
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    print(f"# timing {args.steps} sweeps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     e0.record(stream)
-    for k in range(args.steps):
-        g.sweep(1)
+    g.sweep(args.steps)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = e0.elapsed_time(e1)
     phase_ms, launches = g.get_timing()
+    count_ms, scatter_ms, rebins = g.get_rebin_timing()
     g.set_timing(False)
     z, bp, counts = g.measure_pressure()
+    psi = None
+    if w.get("psi6"):
+        psi6, nb = g.measure_psi6()
+        psi = {"abs": abs(psi6), "re": psi6.real, "im": psi6.imag, "mean_neighbours": nb,
+               "neighbours": "disks within 1.4 sigma"}
     secs = gpu_ms / 1e3
     lifts = counts["lifts"]
     events = counts["lifts"] + counts["frozen"] + counts["walls"] + counts["chains"]
     value = lifts / secs
     sweeps_s = args.steps / secs
     hbm_frac = (HBM_BYTES_PER_DISK * w["n"] * sweeps_s) / (HBM_PEAK_GBS * 1e9)
-    avg_phase_s = phase_ms / 1e3 / max(launches, 1)
-    flop_per_launch = FLOP_PER_EVENT * events / max(launches, 1)
-    achieved_tf = flop_per_launch / avg_phase_s / 1e12
+    avg_launch_s = phase_ms / 1e3 / max(launches, 1)
+    # algorithmic FP64 work per launch: 100 flop per lift, the lifts of the
+    # timed sweeps spread over the launches
+    flop_per_launch = FLOP_PER_LIFT * lifts / max(launches, 1)
+    achieved_tf = flop_per_launch / avg_launch_s / 1e12
+    traffic = measured_traffic(kernel, args.workload)
+    # latency bound of the one-wave-per-cell design: at most CONCURRENT_CELLS
+    # cells run at once, each an event after the other
+    cyc = measured_cycles_per_event(kernel, args.workload)
+    latency = None
+    if cyc is not None:
+        t_step = cyc / (CLOCK_GHZ * 1e9)
+        bound = CONCURRENT_CELLS / t_step * lifts / events
+        latency = {"cycles_per_event": cyc, "t_step_us": t_step * 1e6,
+                   "concurrent_cells": CONCURRENT_CELLS, "lifts_per_s_bound": bound,
+                   "frac": value / bound, "source": f"profiles/{kernel}_{args.workload}_sq_counters.md"}
+    rebin = None
+    if rebins > 0:
+        c_s, s_s = count_ms / 1e3 / rebins, scatter_ms / 1e3 / rebins
+        rebin = {"k_count": {"avg_ms": c_s * 1e3, "bytes": COUNT_BYTES_PER_DISK * w["n"],
+                             "gb_s": COUNT_BYTES_PER_DISK * w["n"] / c_s / 1e9,
+                             "hbm_frac": COUNT_BYTES_PER_DISK * w["n"] / c_s / (HBM_PEAK_GBS * 1e9)},
+                 "k_scatter": {"avg_ms": s_s * 1e3, "bytes": SCATTER_BYTES_PER_DISK * w["n"],
+                               "gb_s": SCATTER_BYTES_PER_DISK * w["n"] / s_s / 1e9,
+                               "hbm_frac": SCATTER_BYTES_PER_DISK * w["n"] / s_s / (HBM_PEAK_GBS * 1e9)}}
     line = {
-        "metric": "EC collisions (lifts)/sec, 1 MI355X, N=1M eta=0.72",
+        "metric": "EC collisions (lifts)/sec, 1 MI355X, " + w["label"],
         "value": value,
         "unit": "lifts/s",
         "n_gpus": 1,
@@ -205,11 +290,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if precision == "fp64" else "f32-screen+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_disks": w["n"], "eta": w["eta"],
                    "cells_per_side": w["cells"], "ell": w["ell"], "directions": "isotropic",
-                   "precision": args.precision,
+                   "precision": precision,
                    "schedule": "phase-launches" if kernel == "k_phase" else "one-launch",
                    "start": "lattice",
                    "sweeps_before_timing": args.warmup},
@@ -217,36 +302,38 @@ def main():
         "events_per_s": events / secs,
         "counts": counts,
         "z_timed_sweeps": z,
+        "beta_p_sigma2_timed_sweeps": bp,
+        "psi6": psi,
         "hbm_frac_whole_sweep": hbm_frac,
         "wall_s": wall,
         "roofline": {"bound": "alu", "kernel": kernel, "achieved": achieved_tf,
                      "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VECTOR_PEAK_TF,
-                     "traffic": measured_traffic(kernel, args.workload),
-                     "avg_launch_ms": avg_phase_s * 1e3, "launches": launches,
+                     "traffic": traffic,
+                     "traffic_over_algorithmic": (traffic / (HBM_BYTES_PER_DISK * w["n"])
+                                                  if traffic is not None and kernel == "k_sweep_cells"
+                                                  else None),
+                     "flop_per_lift": FLOP_PER_LIFT,
+                     "lifts_per_launch": lifts / max(launches, 1),
+                     "avg_launch_ms": avg_launch_s * 1e3, "launches": launches,
                      "kernel_share_of_sweep": phase_ms / gpu_ms},
+        "latency_bound": latency,
+        "rebin": rebin,
     }
     if not args.no_cpu_baseline:
-        print("# CPU oracle baseline", file=sys.stderr, flush=True)
+        print("# CPU oracle baseline (phase-parallel)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
 
 
-def bench_batch(args, torch, P):
-    """Aggregate lifts/s of the 64-system ensemble in the batched form, and the
-    same sweeps run system by system (solo launches, one system after another)."""
-    cfgs = inputs.batch_systems(64, seed=0)
-    flags = SCHEDULE_FLAGS[args.schedule](P)
-    ps = [P.make_params(c["n"], c["eta"], c["ell"], c["cells"], dir_mode=c["dir_mode"],
-                        seed=c["seed"], system=i, flags=flags) for i, c in enumerate(cfgs)]
-    torch.cuda.set_device(0)
+def _batch_run(P, torch, ps, args, schedule_tune=True):
+    """Build the batch, autotune its schedule, warm up, time args.steps sweeps;
+    returns (lifts/s, events/s, ms/sweep, digests of every system, tuning)."""
     b = P.Batch(ps)
-    print(f"# batch64: {len(ps)} systems, sum N = {sum(c['n'] for c in cfgs)}", file=sys.stderr,
-          flush=True)
     b.sweep(1)
-    cpb, trials = b.autotune(trial_sweeps=2)
+    tuned = b.autotune(trial_sweeps=2) if schedule_tune else None
     b.set_graph(True)
     b.sweep(max(args.warmup - 1, 0))
     b.stream.synchronize()
@@ -259,13 +346,43 @@ def bench_batch(args, torch, P):
     e1.record(b.stream)
     b.stream.synchronize()
     secs = e0.elapsed_time(e1) / 1e3
-    lifts = 0
-    events = 0
+    lifts = events = 0
+    digs = []
     for s in b.systems:
         _, _, c = s.measure_pressure()
         lifts += c["lifts"]
         events += c["lifts"] + c["frozen"] + c["walls"] + c["chains"]
+        digs.append(s.get_digests(args.steps))
+    b.close()
+    return lifts / secs, events / secs, secs * 1e3 / args.steps, digs, tuned
+
+
+def bench_batch(args, torch, P):
+    """Aggregate lifts/s of the 64-system ensemble in the batched form, in the
+    requested precision (default: FP32 screening with FP64 commits), the same
+    sweeps in the other precision (digests compared system by system), and the
+    same sweeps run system by system (solo launches, one after another)."""
+    cfgs = inputs.batch_systems(64, seed=0)
+    flags = SCHEDULE_FLAGS[args.schedule](P)
+    precision = args.precision or "fp32-screen"
+    other = "fp64" if precision == "fp32-screen" else "fp32-screen"
+    code = {"fp64": P.EC_PREC_FP64, "fp32-screen": P.EC_PREC_FP32_SCREEN}
+
+    def params(prec):
+        return [P.make_params(c["n"], c["eta"], c["ell"], c["cells"], dir_mode=c["dir_mode"],
+                              seed=c["seed"], system=i, flags=flags, precision=code[prec])
+                for i, c in enumerate(cfgs)]
+
+    torch.cuda.set_device(0)
+    ps = params(precision)
+    print(f"# batch64: {len(ps)} systems, sum N = {sum(c['n'] for c in cfgs)}, {precision}",
+          file=sys.stderr, flush=True)
+    value, ev_s, ms, digs, (sched, cpb, trials) = _batch_run(P, torch, ps, args)
+    print(f"# batch64: {other} for the same sweeps", file=sys.stderr, flush=True)
+    value_o, _, ms_o, digs_o, _ = _batch_run(P, torch, params(other), args)
+    same = all(np.array_equal(a, b) for a, b in zip(digs, digs_o))
     # the same sweeps, system by system
+    print("# batch64: solo runs", file=sys.stderr, flush=True)
     solo_secs = 0.0
     st = torch.cuda.Stream()
     for p in ps:
@@ -282,26 +399,28 @@ def bench_batch(args, torch, P):
         g.close()
     line = {
         "metric": "EC collisions (lifts)/sec, 1 MI355X, 64-system batch (aggregate)",
-        "value": lifts / secs,
+        "value": value,
         "unit": "lifts/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": secs * 1e3 / args.steps,
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if precision == "fp64" else "f32-screen+f64",
         "data": "synthetic",
         "config": {"workload": "batch64", "n_systems": len(ps),
                    "sum_n": int(sum(c["n"] for c in cfgs)), "eta_range": [0.30, 0.72],
-                   "ell": 20.0, "cells_per_block": cpb,
-                   "schedule": "one-launch" if args.schedule == "one-launch" else "phase-launches",
+                   "ell": 20.0, "precision": precision, "schedule": sched, "cells_per_block": cpb,
                    "hip_graph": True},
-        "events_per_s": events / secs,
+        "events_per_s": ev_s,
         "autotune_trial_ms": trials,
+        "other_precision": {"precision": other, "value": value_o, "ms_per_step": ms_o,
+                            "digests_identical": same,
+                            "speedup_of_this_precision": ms_o / ms},
         "solo_sequential_s": solo_secs,
-        "speedup_vs_solo_sequential": solo_secs / secs,
+        "speedup_vs_solo_sequential": solo_secs / (ms * args.steps / 1e3),
     }
     print(json.dumps(line), flush=True)
 

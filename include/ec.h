@@ -100,6 +100,28 @@ typedef enum {
  * make at most 256 lifts (device error bit 32 beyond).  The systems of a
  * batch share it. */
 #define EC_FLAG_REJECT 8u
+/* Debug: after every sweep, check every pair of disks in neighbouring cells
+ * (all pairs for one periodic cell) for a distance below sigma (1 - 1e-12),
+ * the bound rounding may reach on touching disks.  A pair found sets a device
+ * error: the next synchronising call returns EC_E_OVERLAP, and ec_last_error
+ * names the sweep, the number of such pairs and the first pair (the race and
+ * overlap check of the method: disks of two cells run at once never
+ * interpenetrate when the colour phases keep neighbouring cells apart,
+ * Sec. 3.4 step 4).  Costs one pass over the neighbour pairs per sweep. */
+#define EC_FLAG_CHECK_OVERLAP 16u
+/* The striped decomposition with rejection, the variant Sec. 3.4 compares
+ * against (Fig. 3 "stripes"): cells_per_side stripes of width L/C > 2 sigma
+ * span the box, horizontal on even sweeps with chains along x, vertical on
+ * odd sweeps with chains along y, each with a random sign (dir_mode must be
+ * EC_DIR_XY); a random
+ * shift across the stripes and a random first colour per sweep; the two
+ * colours run one after the other, one wavefront per stripe; a chain that
+ * hits a disk of a neighbouring stripe is rejected and undone (at most 1024
+ * moves per chain, device error bit 32 beyond).  Tallies as EC_FLAG_REJECT.
+ * FP64, no EC_FLAG_REJECT (implied); a stripe's disks must fit one CU's LDS
+ * (EC_E_UNSUPPORTED).  Sec. 4 explains why isotropic chains suit stripes
+ * badly; this is a comparison variant, not the method. */
+#define EC_FLAG_STRIPES 32u
 
 typedef struct {
   uint32_t abi_version;     /* must equal EC_ABI_VERSION                                    */
@@ -248,14 +270,22 @@ ec_status ec_get_cell_digests(ec_system sys, uint64_t* out);
 ec_status ec_get_sweep_count(ec_system sys, int64_t* sweeps);
 
 /* Timing of the simulation-cell kernels: with on != 0, every later ec_sweep
- * records HIP events around each launch of the simulation-cell kernel on the
- * system's stream (one per sweep by default, four with EC_FLAG_PHASE_LAUNCHES,
- * one for the periodic cell), synchronises after each sweep and adds the
- * durations up.  Switching on or off clears the totals.  Off by default
- * (sweeps stay asynchronous). */
+ * records HIP events on the system's stream around each launch of the
+ * simulation-cell kernel (one per sweep by default, four with
+ * EC_FLAG_PHASE_LAUNCHES, one for the periodic cell) and around the two
+ * rebin kernels (cell of every disk, scatter by cell), without waiting for
+ * them: the durations are read when the totals are asked for, or once 64
+ * timed sweeps are pending (ec_sweep then synchronises).  Switching on or off
+ * clears the totals.  Off by default. */
 ec_status ec_set_timing(ec_system sys, int32_t on);
-/* Summed simulation-cell kernel milliseconds and number of launches timed. */
+/* Summed simulation-cell kernel milliseconds and number of launches timed.
+ * Synchronises. */
 ec_status ec_get_timing(ec_system sys, double* phase_ms, int64_t* launches);
+/* Summed milliseconds of the two rebin kernels (count: cell of every disk;
+ * scatter: ids grouped by cell) over the timed sweeps of a walled system, and
+ * the number of sweeps (0 for one periodic cell).  Synchronises. */
+ec_status ec_get_rebin_timing(ec_system sys, double* count_ms, double* scatter_ms,
+                              int64_t* sweeps);
 
 /* One-launch sweep (walled cells, default schedule): upper limit of one
  * cell's wait for its neighbours of earlier phases, in seconds (default 60).
@@ -275,14 +305,29 @@ const char* ec_last_error(ec_system sys);
 
 /* ---- Batched form -------------------------------------------------------
  * Several walled systems (C >= 4) advanced together: every step of a sweep
- * (rebin, draws, each colour phase of Sec. 3.4) is one launch over all of
- * them, so small systems fill the GPU together.  The schedule (shared
- * launches, an optional HIP graph per sweep, cells per workgroup) never
- * changes a trajectory: system i of a batch follows exactly the sweeps of a
- * solo system with the same parameters (its seed and `system` index key its
+ * (rebin, draws, the simulation cells of Sec. 3.4) is one launch over all of
+ * them, so small systems fill the GPU together.  The schedule (below, with
+ * an optional HIP graph per sweep and the cells per workgroup) never changes
+ * a trajectory: system i of a batch follows exactly the sweeps of a solo
+ * system with the same parameters (its seed and `system` index key its
  * random streams).  Intended callers: ensembles of independent runs, such as
  * a density scan.
+ *
+ * Schedules of the simulation cells of a batch sweep:
+ *   EC_SCHEDULE_READY_QUEUE (default): one persistent launch for every cell
+ *     of every system; a cell is appended to a device queue as soon as its
+ *     earlier-phase neighbours in its own system are done, and the resident
+ *     wavefronts take the queue in order (no wavefront waits while holding a
+ *     slot, no system waits for another's slowest cell);
+ *   EC_SCHEDULE_ONE_LAUNCH: one launch, each system's cells in phase order
+ *     with per-cell dependency waits (the single-system default);
+ *   EC_SCHEDULE_PHASE_LAUNCHES: one launch per colour phase.
+ * EC_FLAG_ONE_LAUNCH / EC_FLAG_PHASE_LAUNCHES in the parameters select the
+ * initial schedule; ec_batch_set_schedule and ec_batch_autotune change it.
  */
+#define EC_SCHEDULE_PHASE_LAUNCHES 0
+#define EC_SCHEDULE_ONE_LAUNCH 1
+#define EC_SCHEDULE_READY_QUEUE 2
 typedef struct ec_batch_s* ec_batch;
 
 /* Device bytes for a batch of n_sys systems ps[0..n_sys): their workspaces
@@ -315,12 +360,19 @@ ec_status ec_batch_set_graph(ec_batch b, int32_t on);
  * (EC_E_UNSUPPORTED if the LDS of that many cells exceeds 160 KiB). */
 ec_status ec_batch_set_cells_per_block(ec_batch b, int32_t cells_per_block);
 
-/* Time trial_sweeps sweeps for each cells-per-workgroup choice, each from a
- * snapshot of the current state, keep the fastest and put the state back
- * (sweep counts included): the batch continues as if no trial had run.
- * cpb_out (may be NULL) receives the choice, ms_out[3] (may be NULL) the
- * trial times for 1, 2, 4 (-1 where not allowed).  Synchronises. */
-ec_status ec_batch_autotune(ec_batch b, int32_t trial_sweeps, int32_t* cpb_out, double* ms_out);
+/* Schedule of the simulation cells (EC_SCHEDULE_*; EC_E_INVALID otherwise).
+ * Synchronises. */
+ec_status ec_batch_set_schedule(ec_batch b, int32_t schedule);
+
+/* Time trial_sweeps sweeps for each schedule and each cells-per-workgroup
+ * choice (1, 2, 4), each from a snapshot of the current state, keep the
+ * fastest pair and put the state back (sweep counts included): the batch
+ * continues as if no trial had run.  schedule_out and cpb_out (may be NULL)
+ * receive the choice, ms_out[9] (may be NULL) the trial times, index
+ * 3 * schedule + (0, 1, 2 for 1, 2, 4 cells), -1 where not allowed.
+ * Synchronises. */
+ec_status ec_batch_autotune(ec_batch b, int32_t trial_sweeps, int32_t* schedule_out,
+                            int32_t* cpb_out, double* ms_out);
 
 /* Text of the last batch-level error ("" if none). */
 const char* ec_batch_last_error(ec_batch b);

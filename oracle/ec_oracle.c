@@ -473,8 +473,16 @@ static int check_params(const orc_params* p) {
   if (p->eta >= ORC_PI / (2.0 * sqrt(3.0))) return -1;
   if (p->cells < 1) return -1;
   if (p->cells > 1 && (p->cells < 4 || (p->cells & 1))) return -1;
-  if (p->cells > 1 && p->dir_mode != ORC_DIR_ISO) return -1;
   double L = orc_box_length(p->n, p->sigma, p->eta);
+  if (p->boundary == ORC_BOUNDARY_STRIPES) {
+    /* stripes wider than 2 sigma (frozen disks come from the two neighbours),
+     * a box longer than 2 sigma (nearest images along the stripe), chains
+     * along the stripes */
+    if (p->cells < 4 || (p->cells & 1) || p->dir_mode != ORC_DIR_XY) return -1;
+    if (!(L / (double)p->cells > 2.0 * p->sigma) || !(L > 2.0 * p->sigma)) return -1;
+    return 0;
+  }
+  if (p->cells > 1 && p->dir_mode != ORC_DIR_ISO) return -1;
   if (p->cells == 1 && !(L > 2.0 * p->sigma)) return -1;
   if (p->cells > 1 && !(L / (double)p->cells > p->sigma)) return -1;
   if (p->boundary > ORC_BOUNDARY_REJECT || (p->boundary == ORC_BOUNDARY_REJECT && p->cells == 1)) return -1;
@@ -701,6 +709,218 @@ static void sweep_cells(const orc_params* p, double* x, double* y, int64_t sweep
 
 void orc_set_threads(int32_t n) { g_threads = n > 1 ? n : 1; }
 
+/* ------------------------------------------------------------------------ */
+/* Striped decomposition with rejection (Sec. 3.4, Fig. 3 "stripes"; Sec. 4) */
+/* ------------------------------------------------------------------------ */
+/* Disks of one stripe move along it: coordinate a (along the stripe, periodic
+ * in [0, L)) and v (across it, local to the stripe).  Frozen disks are those
+ * of the two neighbouring stripes within sigma of it. */
+typedef struct {
+  double L, half_L, sigma, cap;
+  int64_t n;                         /* N: pseudo event id N+2, chain end N+3 */
+  int64_t n_own, n_fr;
+  double *oa, *ov;                   /* own disks (a updated in place)        */
+  const int64_t* ogid;
+  const double *fa, *fv;             /* frozen disks                          */
+  const int64_t* fgid;
+  double* acc_delta;
+  uint64_t* acc_cnt;
+  uint64_t digest, n_events;
+  int64_t u_n, u_cap, *u_i;          /* undo log of the running chain          */
+  double* u_a;
+} stripe_ctx;
+
+static void stripe_digest(stripe_ctx* sx, int kind, int64_t gid, double s) {
+  uint64_t sb;
+  memcpy(&sb, &s, sizeof sb);
+  const uint64_t r = sb ^ ((uint64_t)gid * DIGEST_K1) ^ ((uint64_t)kind << 56);
+  sx->digest ^= mix64(r ^ (sx->n_events * DIGEST_K2));
+  sx->n_events += 1;
+}
+
+/* Contact distance along the stripe to a disk at offset (ra, rv): the
+ * collision distance of Sec. 3.2 with the direction (1, 0). */
+static double stripe_contact(double ra, double rv, double sigma) {
+  const double disc = fma(-rv, rv, sigma * sigma);
+  if (ra > 0.0 && disc > 0.0) {
+    double s = ra - sqrt(disc);
+    if (s < 0.0) s = 0.0;
+    return s;
+  }
+  return INFINITY;
+}
+
+static double stripe_image(double r, const stripe_ctx* sx) {
+  if (r < -sx->half_L) r += sx->L;
+  else if (r >= sx->half_L) r -= sx->L;
+  return r;
+}
+
+/* Move own disk i by s along the stripe in direction sgn (+1 or -1). */
+static void stripe_move(stripe_ctx* sx, int64_t i, double s, int sgn) {
+  double a = sgn > 0 ? sx->oa[i] + s : sx->oa[i] - s;
+  if (a >= sx->L) a -= sx->L;
+  else if (a < 0.0) a += sx->L;
+  sx->oa[i] = a;
+}
+
+/* A chain along the stripe in direction sgn: the chain and its reverse (the
+ * opposite direction from the last disk) are proposed alike, and a chain is
+ * rejected exactly when its reverse is, so rejection keeps detailed balance. */
+static void stripe_chain(stripe_ctx* sx, int64_t a, double ell, int sgn) {
+  double rem = ell;
+  double chain_delta = 0.0;
+  uint64_t chain_lifts = 0;
+  sx->u_n = 0;
+  sx->acc_cnt[ORC_CNT_CHAINS] += 1;
+  for (;;) {
+    const double aa = sx->oa[a], av = sx->ov[a];
+    double best_s = INFINITY;
+    int64_t best_gid = INT64_MAX, best_j = -1;
+    int best_kind = 0;
+    for (int64_t j = 0; j < sx->n_own; ++j) {
+      if (j == a) continue;
+      const double ra = stripe_image(sx->oa[j] - aa, sx);
+      const double s = stripe_contact(sgn > 0 ? ra : -ra, sx->ov[j] - av, sx->sigma);
+      if (s < best_s || (s == best_s && s != INFINITY && sx->ogid[j] < best_gid)) {
+        best_s = s; best_gid = sx->ogid[j]; best_j = j; best_kind = ORC_EV_LIFT;
+      }
+    }
+    for (int64_t j = 0; j < sx->n_fr; ++j) {
+      const double ra = stripe_image(sx->fa[j] - aa, sx);
+      const double s = stripe_contact(sgn > 0 ? ra : -ra, sx->fv[j] - av, sx->sigma);
+      if (s < best_s || (s == best_s && s != INFINITY && sx->fgid[j] < best_gid)) {
+        best_s = s; best_gid = sx->fgid[j]; best_j = j; best_kind = ORC_EV_FROZEN;
+      }
+    }
+    /* nearest images are exact for flights up to L/2 - sigma only */
+    const double lim = best_s < rem ? best_s : rem;
+    if (lim > sx->cap) {
+      stripe_digest(sx, ORC_EV_PSEUDO, sx->n + 2, sx->cap);
+      if (sx->u_n == sx->u_cap) {
+        sx->u_cap = sx->u_cap ? 2 * sx->u_cap : 64;
+        sx->u_i = (int64_t*)realloc(sx->u_i, sizeof(int64_t) * (size_t)sx->u_cap);
+        sx->u_a = (double*)realloc(sx->u_a, sizeof(double) * (size_t)sx->u_cap);
+      }
+      sx->u_i[sx->u_n] = a; sx->u_a[sx->u_n] = sx->oa[a]; sx->u_n += 1;
+      stripe_move(sx, a, sx->cap, sgn);
+      rem = rem - sx->cap;
+      sx->acc_cnt[ORC_CNT_PSEUDO] += 1;
+      continue;
+    }
+    if (!(best_s < rem)) {
+      stripe_digest(sx, ORC_EV_END, sx->n + 3, rem);
+      stripe_move(sx, a, rem, sgn);
+      sx->acc_delta[0] += chain_delta;  /* accepted */
+      sx->acc_cnt[ORC_CNT_LIFTS] += chain_lifts;
+      break;
+    }
+    stripe_digest(sx, best_kind, best_gid, best_s);
+    if (sx->u_n == sx->u_cap) {
+      sx->u_cap = sx->u_cap ? 2 * sx->u_cap : 64;
+      sx->u_i = (int64_t*)realloc(sx->u_i, sizeof(int64_t) * (size_t)sx->u_cap);
+      sx->u_a = (double*)realloc(sx->u_a, sizeof(double) * (size_t)sx->u_cap);
+    }
+    sx->u_i[sx->u_n] = a; sx->u_a[sx->u_n] = sx->oa[a]; sx->u_n += 1;
+    stripe_move(sx, a, best_s, sgn);
+    rem = rem - best_s;
+    if (best_kind == ORC_EV_FROZEN) {
+      /* a disk of a neighbouring stripe: the chain is rejected and undone */
+      sx->acc_cnt[ORC_CNT_FROZEN] += 1;
+      for (int64_t u = sx->u_n - 1; u >= 0; --u) sx->oa[sx->u_i[u]] = sx->u_a[u];
+      break;
+    }
+    const double rd = stripe_image(sx->oa[best_j] - sx->oa[a], sx);
+    chain_delta = chain_delta + (sgn > 0 ? rd : -rd);
+    chain_lifts += 1;
+    a = best_j;
+  }
+}
+
+static void sweep_stripes(const orc_params* p, double* x, double* y, int64_t sweep,
+                          double* acc_delta, uint64_t* acc_cnt, uint64_t* digest_out) {
+  const int32_t S = p->cells;
+  const double L = orc_box_length(p->n, p->sigma, p->eta), half_L = 0.5 * L;
+  const double h = L / (double)S, sigma = p->sigma;
+  /* even sweeps: horizontal stripes, chains along +x; odd sweeps: vertical
+   * stripes, chains along +y */
+  double* along = (sweep & 1) ? y : x;
+  const double* across = (sweep & 1) ? x : y;
+  /* draws: the shift of the stripes across their direction, and which of
+   * the two stripe colours goes first */
+  stream_t st;
+  stream_init(&st, p->seed, KIND_SWEEP, (uint64_t)sweep, (uint64_t)p->system, 0);
+  const double shift = u01(stream_next(&st)) * h;
+  const int first = (int)draw_index(&st, 2);
+  int32_t* stripe_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)p->n);
+  for (int64_t i = 0; i < p->n; ++i) {
+    int64_t k = (int64_t)floor(shifted(across[i], shift, L) / h);
+    if (k > S - 1) k = S - 1;
+    stripe_of[i] = (int32_t)k;
+  }
+  int64_t* start = (int64_t*)malloc(sizeof(int64_t) * (size_t)(S + 1));
+  int64_t* ids = (int64_t*)malloc(sizeof(int64_t) * (size_t)p->n);
+  build_lists(stripe_of, p->n, S, start, ids);
+  uint64_t total = 0;
+  for (int32_t q = 0; q < 2; ++q) {
+    for (int32_t k = 0; k < S; ++k) {
+      if ((k & 1) != (first ^ q)) continue;
+      const double origin = (double)k * h;
+      const int64_t n_c = start[k + 1] - start[k];
+      stripe_ctx sx;
+      memset(&sx, 0, sizeof sx);
+      sx.L = L; sx.half_L = half_L; sx.sigma = sigma; sx.cap = half_L - sigma; sx.n = p->n;
+      sx.n_own = n_c;
+      sx.ogid = &ids[start[k]];
+      sx.oa = (double*)malloc(sizeof(double) * (size_t)(n_c > 0 ? n_c : 1));
+      sx.ov = (double*)malloc(sizeof(double) * (size_t)(n_c > 0 ? n_c : 1));
+      for (int64_t t = 0; t < n_c; ++t) {
+        const int64_t i = sx.ogid[t];
+        sx.oa[t] = along[i];
+        sx.ov[t] = local_coord(across[i], shift, origin, L, half_L);
+      }
+      int64_t cap_f = 64;
+      double* fa = (double*)malloc(sizeof(double) * (size_t)cap_f);
+      double* fv = (double*)malloc(sizeof(double) * (size_t)cap_f);
+      int64_t* fg = (int64_t*)malloc(sizeof(int64_t) * (size_t)cap_f);
+      for (int32_t side = -1; side <= 1; side += 2) {
+        const int32_t nk = (k + side + S) % S;
+        for (int64_t t = start[nk]; t < start[nk + 1]; ++t) {
+          const int64_t i = ids[t];
+          const double v = local_coord(across[i], shift, origin, L, half_L);
+          if (!(v >= -sigma && v <= h + sigma)) continue;
+          if (sx.n_fr == cap_f) {
+            cap_f *= 2;
+            fa = (double*)realloc(fa, sizeof(double) * (size_t)cap_f);
+            fv = (double*)realloc(fv, sizeof(double) * (size_t)cap_f);
+            fg = (int64_t*)realloc(fg, sizeof(int64_t) * (size_t)cap_f);
+          }
+          fa[sx.n_fr] = along[i]; fv[sx.n_fr] = v; fg[sx.n_fr] = i; sx.n_fr++;
+        }
+      }
+      sx.fa = fa; sx.fv = fv; sx.fgid = fg;
+      sx.acc_delta = &acc_delta[k];
+      sx.acc_cnt = &acc_cnt[(int64_t)k * ORC_CNT_NCOL];
+      const int64_t n_m = n_c > 0 ? (p->chains_per_cell > 0 ? p->chains_per_cell : n_c) : 0;
+      int64_t* starts = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_m > 0 ? n_m : 1));
+      make_start_list_(p, sweep, k, n_c, n_m, starts);
+      for (int64_t c = 0; c < n_m; ++c) {
+        /* the sign of chain c: the top bit of the first word of its
+         * direction stream (set: against the axis) */
+        stream_t ds;
+        stream_init(&ds, p->seed, KIND_DIR, (uint64_t)sweep, cell_key(p, k), (uint64_t)c);
+        const int sgn = (stream_next(&ds) >> 63) ? -1 : 1;
+        stripe_chain(&sx, starts[c], p->ell, sgn);
+      }
+      for (int64_t t = 0; t < n_c; ++t) along[sx.ogid[t]] = sx.oa[t];
+      total += sx.digest * (2ULL * (uint64_t)k + 1ULL);
+      free(starts); free(fa); free(fv); free(fg); free(sx.oa); free(sx.ov); free(sx.u_i); free(sx.u_a);
+    }
+  }
+  if (digest_out) *digest_out = total;
+  free(stripe_of); free(start); free(ids);
+}
+
 int orc_run(const orc_params* p, double* x, double* y, int64_t sweep0, int64_t n_sweeps,
             double* acc_delta, uint64_t* acc_cnt, uint64_t* digests) {
   if (check_params(p) != 0) return -1;
@@ -708,6 +928,8 @@ int orc_run(const orc_params* p, double* x, double* y, int64_t sweep0, int64_t n
     uint64_t d = 0;
     if (p->cells == 1)
       sweep_periodic(p, x, y, sweep0 + s, acc_delta, acc_cnt, &d);
+    else if (p->boundary == ORC_BOUNDARY_STRIPES)
+      sweep_stripes(p, x, y, sweep0 + s, acc_delta, acc_cnt, &d);
     else
       sweep_cells(p, x, y, sweep0 + s, 4, NULL, 0, acc_delta, acc_cnt, &d, NULL);
     if (digests) digests[s] = d;
@@ -718,7 +940,7 @@ int orc_run(const orc_params* p, double* x, double* y, int64_t sweep0, int64_t n
 int orc_run_cells(const orc_params* p, double* x, double* y, int64_t sweep, int32_t n_phases,
                   const int32_t* cells, int32_t n_cells, double* acc_delta, uint64_t* acc_cnt,
                   uint64_t* cell_digest) {
-  if (check_params(p) != 0 || p->cells == 1) return -1;
+  if (check_params(p) != 0 || p->cells == 1 || p->boundary == ORC_BOUNDARY_STRIPES) return -1;
   if (n_phases < 1 || n_phases > 4) return -1;
   for (int32_t t = 0; t < n_cells; ++t) cell_digest[t] = 0;
   sweep_cells(p, x, y, sweep, n_phases, cells, n_cells, acc_delta, acc_cnt, NULL, cell_digest);

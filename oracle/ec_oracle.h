@@ -24,8 +24,13 @@ enum { ORC_DIR_XY = 0, ORC_DIR_ISO = 1, ORC_DIR_X = 2 };
 enum { ORC_START_REPLACE = 0, ORC_START_DISTINCT = 1 };
 /* What a chain does at a cell wall or a frozen disk (walled cells): reflect
  * with equal angles (Sec. 3.4, Fig. 1 right), or reject the whole chain,
- * the variant of Sec. 3.4 attributed to the striped decomposition. */
-enum { ORC_BOUNDARY_REFLECT = 0, ORC_BOUNDARY_REJECT = 1 };
+ * the variant of Sec. 3.4 attributed to the striped decomposition.
+ * ORC_BOUNDARY_STRIPES: the striped decomposition itself (Sec. 3.4, Fig. 3
+ * "stripes"; Sec. 4): `cells` stripes spanning the box, chains along the
+ * stripes (along x, either sign, in horizontal stripes on even sweeps; along
+ * y in vertical stripes on odd sweeps; dir_mode must be ORC_DIR_XY), a chain
+ * that hits a disk of a neighbouring stripe rejected and undone. */
+enum { ORC_BOUNDARY_REFLECT = 0, ORC_BOUNDARY_REJECT = 1, ORC_BOUNDARY_STRIPES = 2 };
 
 /* Event kinds, also used in the event digest. */
 enum { ORC_EV_LIFT = 1, ORC_EV_FROZEN = 2, ORC_EV_WALL_X = 3, ORC_EV_WALL_Y = 4,

@@ -13,7 +13,7 @@ from . import build as _build
 
 DIR_XY, DIR_ISO, DIR_X = 0, 1, 2
 START_REPLACE, START_DISTINCT = 0, 1
-BOUNDARY_REFLECT, BOUNDARY_REJECT = 0, 1
+BOUNDARY_REFLECT, BOUNDARY_REJECT, BOUNDARY_STRIPES = 0, 1, 2
 EV_LIFT, EV_FROZEN, EV_WALL_X, EV_WALL_Y, EV_PSEUDO, EV_END = 1, 2, 3, 4, 5, 6
 CNT_LIFTS, CNT_FROZEN, CNT_WALLS, CNT_CHAINS, CNT_PSEUDO, CNT_NCOL = 0, 1, 2, 3, 4, 5
 

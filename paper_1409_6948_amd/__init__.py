@@ -6,11 +6,11 @@ the same names.  There is no CPU fallback: importing the binding without the
 built library raises.
 """
 from .ec import (EC_DIR_ISOTROPIC, EC_DIR_X, EC_DIR_XY, EC_FLAG_ONE_LAUNCH, EC_FLAG_PHASE_LAUNCHES,
-                 EC_FLAG_REJECT, EC_FLAG_SCAN_SEARCH, EC_PREC_FP32_SCREEN, EC_PREC_FP64, EC_START_DISTINCT, EC_START_REPLACE, Batch, ECError, System, batch_workspace_bytes,
+                 EC_FLAG_CHECK_OVERLAP, EC_FLAG_REJECT, EC_FLAG_SCAN_SEARCH, EC_FLAG_STRIPES, EC_PREC_FP32_SCREEN, EC_PREC_FP64, EC_START_DISTINCT, EC_START_REPLACE, Batch, ECError, System, batch_workspace_bytes,
                  gr_normalize, lib_path, load_library, make_params, psi_autocorrelation,
                  workspace_bytes)
 
 __all__ = ["EC_DIR_ISOTROPIC", "EC_DIR_X", "EC_DIR_XY", "EC_FLAG_ONE_LAUNCH", "EC_FLAG_PHASE_LAUNCHES",
-           "EC_FLAG_REJECT", "EC_FLAG_SCAN_SEARCH", "EC_PREC_FP32_SCREEN", "EC_PREC_FP64", "EC_START_DISTINCT", "EC_START_REPLACE", "Batch", "ECError", "System",
+           "EC_FLAG_CHECK_OVERLAP", "EC_FLAG_REJECT", "EC_FLAG_SCAN_SEARCH", "EC_FLAG_STRIPES", "EC_PREC_FP32_SCREEN", "EC_PREC_FP64", "EC_START_DISTINCT", "EC_START_REPLACE", "Batch", "ECError", "System",
            "batch_workspace_bytes", "gr_normalize", "lib_path", "load_library", "make_params",
            "psi_autocorrelation", "workspace_bytes"]

@@ -21,7 +21,7 @@ constexpr double kPi = 3.14159265358979323846;
 struct Layout {
   size_t dev, sweep_ctr, x, y, cell_of, cell_ids, cell_count, cell_fill, cell_start, acc_delta, acc_cnt,
       ring, cell_digest, draws, err, red, chain_start, chain_dir, shuffle, dbg, psi, psi_part, psi_red,
-      gr, queue, cell_done, psi_nb, psi_err, total;
+      gr, queue, cell_done, psi_nb, psi_err, ovl, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -30,16 +30,19 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // device clock.
 constexpr int64_t kDefaultDepWaitTicks = int64_t(60) * 100000000;
 
-Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell) {
+// sweep_only: no positions (the caller's) and no observables, for the
+// allocation-free entry point whose state lives in the static scratch.
+Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell, bool sweep_only = false) {
   Layout l;
   size_t o = 0;
   size_t nc = (size_t)C * (size_t)C;
+  const size_t no = sweep_only ? 0 : (size_t)n;  // disks of the per-disk arrays left out
   size_t max_chains = chains_per_cell > 0 ? nc * (size_t)chains_per_cell : (size_t)n;
   if (C == 1) max_chains = 0;  // the periodic kernel draws its chains itself
   l.dev = o;        o = align256(o + sizeof(ec::Dev));
   l.sweep_ctr = o;  o = align256(o + 8);
-  l.x = o;          o = align256(o + 8 * (size_t)n);
-  l.y = o;          o = align256(o + 8 * (size_t)n);
+  l.x = o;          o = align256(o + 8 * no);
+  l.y = o;          o = align256(o + 8 * no);
   l.cell_of = o;    o = align256(o + 4 * (size_t)n);
   l.cell_ids = o;   o = align256(o + 4 * (size_t)n);
   l.cell_count = o; o = align256(o + 4 * nc);
@@ -56,14 +59,15 @@ Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell) {
   l.chain_dir = o;  o = align256(o + 16 * max_chains);
   l.shuffle = o;    o = align256(o + (C == 1 ? 0 : 4 * (size_t)n));
   l.dbg = o;        o = align256(o + 8 * ec::kDebugWords);
-  l.psi = o;        o = align256(o + 16 * (size_t)n);
-  l.psi_part = o;   o = align256(o + 24 * (((size_t)n + 255) / 256));
-  l.psi_red = o;    o = align256(o + 32);
-  l.gr = o;         o = align256(o + 8 * (size_t)(ec::kMaxGrBins + 1));
+  l.psi = o;        o = align256(o + 16 * no);
+  l.psi_part = o;   o = align256(o + 24 * ((no + 255) / 256));
+  l.psi_red = o;    o = align256(o + (sweep_only ? 0 : 32));
+  l.gr = o;         o = align256(o + (sweep_only ? 0 : 8 * (size_t)(ec::kMaxGrBins + 1)));
   l.queue = o;      o = align256(o + 8);
   l.cell_done = o;  o = align256(o + 8 * nc);
-  l.psi_nb = o;     o = align256(o + 4 * (size_t)n);
-  l.psi_err = o;    o = align256(o + 16);
+  l.psi_nb = o;     o = align256(o + 4 * no);
+  l.psi_err = o;    o = align256(o + (sweep_only ? 0 : 16));
+  l.ovl = o;        o = align256(o + 32);
   l.total = o;
   return l;
 }
@@ -71,7 +75,18 @@ Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell) {
 struct Derived {
   double L, w;
   int32_t nb, cap_own, cpb, lds_per_cell;
+  int32_t stripe_cap_own, stripe_cap_frozen, stripe_undo;  // striped decomposition only
 };
+
+// Oler's bound for a rectangle a x b: at most (2/sqrt 3) A/s^2 + P/(2s) + 1
+// points with mutual distance >= s.
+int32_t rect_capacity(double a, double b, double sigma) {
+  const double u = a / sigma + 1e-6, v = b / sigma + 1e-6;
+  const double bound = (2.0 / std::sqrt(3.0)) * u * v + (u + v) + 1.0;
+  return ((int32_t)std::ceil(bound) + 63) & ~63;
+}
+// Lifts of one chain the striped kernel can undo.
+constexpr int32_t kStripeUndo = 1024;
 
 // Oler's bound: at most (2/sqrt 3) A/s^2 + P/(2s) + 1 points with mutual
 // distance >= s fit in a convex region of area A and perimeter P.
@@ -83,6 +98,7 @@ int32_t own_capacity(double w, double sigma) {
 }
 
 ec_status validate(const ec_params* p, Derived* out, std::string* why) {
+  *out = Derived{};
   if (!p) { *why = "null parameters"; return EC_E_INVALID; }
   if (p->abi_version != EC_ABI_VERSION) { *why = "abi_version mismatch"; return EC_E_INVALID; }
   if (p->n_disks < 1 || p->n_disks > 0x7FFFFFF0LL) { *why = "n_disks out of range"; return EC_E_INVALID; }
@@ -92,6 +108,11 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
   if ((p->flags & EC_FLAG_REJECT) &&
       (p->cells_per_side == 1 || p->precision != EC_PREC_FP64)) {
     *why = "EC_FLAG_REJECT needs walled cells and FP64"; return EC_E_UNSUPPORTED;
+  }
+  if ((p->flags & EC_FLAG_STRIPES) &&
+      (p->cells_per_side == 1 || p->precision != EC_PREC_FP64 || (p->flags & EC_FLAG_REJECT))) {
+    *why = "EC_FLAG_STRIPES needs C >= 4 stripes and FP64 (it implies rejection)";
+    return EC_E_UNSUPPORTED;
   }
   if ((p->flags & EC_FLAG_PHASE_LAUNCHES) && (p->flags & EC_FLAG_ONE_LAUNCH)) {
     *why = "EC_FLAG_PHASE_LAUNCHES and EC_FLAG_ONE_LAUNCH exclude each other"; return EC_E_INVALID;
@@ -112,6 +133,28 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
       *why = "one periodic cell supports at most 2048 disks"; return EC_E_UNSUPPORTED;
     }
     out->w = L; out->nb = 0; out->cap_own = 0; out->cpb = 1; out->lds_per_cell = 0;
+  } else if (p->flags & EC_FLAG_STRIPES) {
+    if (C < 4 || (C & 1)) { *why = "the number of stripes must be even and >= 4"; return EC_E_INVALID; }
+    if (p->dir_mode != EC_DIR_XY) {
+      *why = "stripes need chains along them (dir_mode EC_DIR_XY)"; return EC_E_INVALID;
+    }
+    const double w = L / (double)C;
+    if (!(w > 2.0 * p->sigma)) { *why = "stripe width must exceed 2 sigma"; return EC_E_INVALID; }
+    if (p->n_disks > (int64_t(1) << 29) - 4) {
+      *why = "at most 2^29 - 4 disks"; return EC_E_UNSUPPORTED;
+    }
+    out->w = w;
+    out->nb = 0;
+    out->cap_own = 0;
+    out->cpb = 1;
+    out->stripe_cap_own = rect_capacity(L, w, p->sigma);
+    out->stripe_cap_frozen = 2 * rect_capacity(L, p->sigma, p->sigma);
+    out->stripe_undo = kStripeUndo;
+    out->lds_per_cell = ec::stripe_lds_bytes(out->stripe_cap_own, out->stripe_cap_frozen, kStripeUndo);
+    if (out->lds_per_cell > 160 * 1024) {
+      *why = "a stripe's disks exceed the LDS of one CU (fewer disks or more stripes)";
+      return EC_E_UNSUPPORTED;
+    }
   } else {
     if (C < 4 || (C & 1)) { *why = "cells_per_side must be 1 or even and >= 4"; return EC_E_INVALID; }
     if (p->dir_mode != EC_DIR_ISOTROPIC) {
@@ -128,8 +171,7 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
     out->nb = nb;
     out->cap_own = own_capacity(w, p->sigma);
     out->lds_per_cell =
-        ec::cell_lds_layout(nb + 2, out->cap_own, p->precision == EC_PREC_FP32_SCREEN,
-                            (p->flags & EC_FLAG_REJECT) != 0).bytes;
+        ec::cell_lds_layout(nb + 2, out->cap_own, (p->flags & EC_FLAG_REJECT) != 0).bytes;
     // Default: four cells (four waves) per workgroup when their LDS fits one CU.
     // The waves of one workgroup go to the four SIMDs of one CU; one-wave
     // workgroups leave the SIMD choice to the dispatcher, which has been
@@ -169,11 +211,13 @@ struct ec_system_s {
   hipStream_t stream;
   int64_t sweeps;
   std::string last_error;
-  // optional phase-kernel timing
+  // optional kernel timing: a pool of event sets, one per sweep, read when
+  // the pool is full or the totals are asked for
   bool timing;
-  ec::PhaseEvents ev;
-  double phase_ms;
-  int64_t phase_launches;
+  std::vector<ec::PhaseEvents> ev;
+  int pending;
+  double phase_ms, count_ms, scatter_ms;
+  int64_t phase_launches, rebin_launches;
   // pair histogram series (pressure route)
   double gr_rmax;
   int32_t gr_bins;
@@ -247,11 +291,15 @@ ec::LaunchShape shape_of(const ec::Dev& d, const ec_params& p) {
   sh.max_n = d.n;
   sh.max_chains = d.chains_per_cell > 0 ? (int64_t)d.C * d.C * d.chains_per_cell : d.n;
   sh.max_cells = d.C * d.C;
+  sh.max_cells_side = d.C;
   sh.max_active = (d.C / 2) * (d.C / 2);
   sh.cpb = d.cells_per_block;
   sh.max_lds_per_cell = d.lds_per_cell;
   sh.one_launch = d.C > 1 && !(p.flags & EC_FLAG_PHASE_LAUNCHES);  // a system swept alone
   sh.reject = d.reject != 0;
+  sh.check_overlap = d.check_overlap != 0;
+  sh.stripes = d.stripes != 0;
+  if (sh.stripes) sh.one_launch = false;
   return sh;
 }
 
@@ -277,27 +325,10 @@ void screen_bounds(ec::Dev* d) {
   d->scr_e = (float)e;
 }
 
-// Create a system in a workspace region (validated parameters); with a
-// batch owner the handle is a view that the batch destroys.
-ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b, size_t ws_bytes,
-                         hipStream_t stream, bool in_batch, ec_system* out) {
-  Layout lay = make_layout(p->n_disks, p->cells_per_side, p->chains_per_cell);
-  if (ws_bytes < lay.total) return EC_E_NOMEM;
-  ec_system s = new (std::nothrow) ec_system_s();
-  if (!s) return EC_E_NOMEM;
-  s->p = *p;
-  s->dv = dv;
-  s->lay = lay;
-  s->stream = stream;
-  s->in_batch = in_batch;
-  s->sweeps = 0;
-  s->timing = false;
-  s->phase_ms = 0.0;
-  s->phase_launches = 0;
-  s->gr_rmax = 0.0;
-  s->gr_bins = 0;
-  s->gr_samples = 0;
-  ec::Dev& d = s->dev;
+// The device record of a system whose workspace region starts at b.
+void fill_record(ec::Dev* out, const ec_params* p, const Derived& dv, unsigned char* b,
+                 const Layout& lay) {
+  ec::Dev& d = *out;
   std::memset(&d, 0, sizeof d);
   d.x = (double*)(b + lay.x);
   d.y = (double*)(b + lay.y);
@@ -326,6 +357,12 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   d.cell_done = (int64_t*)(b + lay.cell_done);
   d.psi_nb = (int32_t*)(b + lay.psi_nb);
   d.psi_err = (unsigned long long*)(b + lay.psi_err);
+  d.ovl = (unsigned long long*)(b + lay.ovl);
+  d.check_overlap = (p->flags & EC_FLAG_CHECK_OVERLAP) ? 1 : 0;
+  d.stripes = (p->flags & EC_FLAG_STRIPES) ? 1 : 0;
+  d.stripe_cap_own = dv.stripe_cap_own;
+  d.stripe_cap_frozen = dv.stripe_cap_frozen;
+  d.stripe_undo = dv.stripe_undo;
   d.dep_wait_ticks = kDefaultDepWaitTicks;
   d.reject = (p->flags & EC_FLAG_REJECT) ? 1 : 0;
   d.search = (p->flags & EC_FLAG_SCAN_SEARCH) ? 1 : 0;
@@ -353,6 +390,31 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   d.cells_per_block = dv.cpb;
   d.seed = p->seed;
   d.system = p->system;
+}
+
+// Create a system in a workspace region (validated parameters); with a
+// batch owner the handle is a view that the batch destroys.
+ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b, size_t ws_bytes,
+                         hipStream_t stream, bool in_batch, ec_system* out) {
+  Layout lay = make_layout(p->n_disks, p->cells_per_side, p->chains_per_cell);
+  if (ws_bytes < lay.total) return EC_E_NOMEM;
+  ec_system s = new (std::nothrow) ec_system_s();
+  if (!s) return EC_E_NOMEM;
+  s->p = *p;
+  s->dv = dv;
+  s->lay = lay;
+  s->stream = stream;
+  s->in_batch = in_batch;
+  s->sweeps = 0;
+  s->timing = false;
+  s->pending = 0;
+  s->phase_ms = s->count_ms = s->scatter_ms = 0.0;
+  s->phase_launches = s->rebin_launches = 0;
+  s->gr_rmax = 0.0;
+  s->gr_bins = 0;
+  s->gr_samples = 0;
+  fill_record(&s->dev, p, dv, b, lay);
+  ec::Dev& d = s->dev;
   s->dev_d = (ec::Dev*)(b + lay.dev);
   s->shape = shape_of(d, *p);
 
@@ -370,6 +432,7 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   if (e == hipSuccess) e = hipMemsetAsync(d.cell_digest, 0, 8 * (size_t)d.C * (size_t)d.C, stream);
   if (e == hipSuccess) e = hipMemsetAsync(d.cell_done, 0, 8 * (size_t)d.C * (size_t)d.C, stream);
   if (e == hipSuccess) e = hipMemsetAsync(d.queue, 0, 8, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.ovl, 0, 32, stream);
   if (e == hipSuccess) e = hipMemsetAsync(d.gr_counts, 0, 8 * (size_t)(ec::kMaxGrBins + 1), stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);  // the host record is copied by now
   if (e != hipSuccess) {
@@ -396,19 +459,42 @@ ec_status ec_init_system(const ec_params* p, void* ws, size_t ws_bytes, void* st
   return init_system_at(p, dv, (unsigned char*)ws, ws_bytes, (hipStream_t)stream, false, out);
 }
 
+// Read the durations of the timed sweeps still held in the event pool.
+static ec_status resolve_timing(ec_system s) {
+  if (!s->timing || s->pending == 0) return EC_OK;
+  EC_HIP(s, hipStreamSynchronize(s->stream));
+  const int nq = (s->shape.periodic || s->shape.one_launch) ? 1 : (s->shape.stripes ? 2 : 4);
+  for (int k = 0; k < s->pending; ++k) {
+    const ec::PhaseEvents& ev = s->ev[(size_t)k];
+    for (int q = 0; q < nq; ++q) {
+      float ms = 0.f;
+      EC_HIP(s, hipEventElapsedTime(&ms, ev.begin[q], ev.end[q]));
+      s->phase_ms += ms;
+      s->phase_launches += 1;
+    }
+    if (!s->shape.periodic) {
+      float m0 = 0.f, m1 = 0.f;
+      EC_HIP(s, hipEventElapsedTime(&m0, ev.rebin[0], ev.rebin[1]));
+      EC_HIP(s, hipEventElapsedTime(&m1, ev.rebin[2], ev.rebin[3]));
+      s->count_ms += m0;
+      s->scatter_ms += m1;
+      s->rebin_launches += 1;
+    }
+  }
+  s->pending = 0;
+  return EC_OK;
+}
+
 ec_status ec_sweep(ec_system s, int64_t n_sweeps) {
   if (!s || n_sweeps < 0) return EC_E_INVALID;
   for (int64_t i = 0; i < n_sweeps; ++i) {
     if (s->timing) {
-      EC_HIP(s, ec::launch_sweep(s->dev_d, s->shape, s->stream, &s->ev));
-      EC_HIP(s, hipStreamSynchronize(s->stream));
-      int nq = (s->shape.periodic || s->shape.one_launch) ? 1 : 4;
-      for (int q = 0; q < nq; ++q) {
-        float ms = 0.f;
-        EC_HIP(s, hipEventElapsedTime(&ms, s->ev.begin[q], s->ev.end[q]));
-        s->phase_ms += ms;
-        s->phase_launches += 1;
+      if (s->pending == (int)s->ev.size()) {
+        ec_status st = resolve_timing(s);
+        if (st != EC_OK) return st;
       }
+      EC_HIP(s, ec::launch_sweep(s->dev_d, s->shape, s->stream, &s->ev[(size_t)s->pending]));
+      s->pending += 1;
     } else {
       EC_HIP(s, ec::launch_sweep(s->dev_d, s->shape, s->stream));
     }
@@ -417,32 +503,65 @@ ec_status ec_sweep(ec_system s, int64_t n_sweeps) {
   return EC_OK;
 }
 
+// Sweeps whose kernel events the pool holds before ec_sweep reads them.
+constexpr int kTimingPool = 64;
+
+static void destroy_events(ec_system s) {
+  for (auto& ev : s->ev) {
+    for (int q = 0; q < 4; ++q) {
+      if (ev.begin[q]) (void)hipEventDestroy(ev.begin[q]);  // cleanup: failures ignored
+      if (ev.end[q]) (void)hipEventDestroy(ev.end[q]);
+      if (ev.rebin[q]) (void)hipEventDestroy(ev.rebin[q]);
+    }
+  }
+  s->ev.clear();
+}
+
 ec_status ec_set_timing(ec_system s, int32_t on) {
   if (!s) return EC_E_INVALID;
   if (on && !s->timing) {
-    for (int q = 0; q < 4; ++q) {
-      EC_HIP(s, hipEventCreate(&s->ev.begin[q]));
-      EC_HIP(s, hipEventCreate(&s->ev.end[q]));
+    s->ev.assign(kTimingPool, ec::PhaseEvents{});
+    for (auto& ev : s->ev) {
+      for (int q = 0; q < 4; ++q) {
+        hipError_t e = hipEventCreate(&ev.begin[q]);
+        if (e == hipSuccess) e = hipEventCreate(&ev.end[q]);
+        if (e == hipSuccess) e = hipEventCreate(&ev.rebin[q]);
+        if (e != hipSuccess) {
+          destroy_events(s);
+          return hip_fail(s, e, "hipEventCreate");
+        }
+      }
     }
     s->timing = true;
   }
   if (!on && s->timing) {
     EC_HIP(s, hipStreamSynchronize(s->stream));
-    for (int q = 0; q < 4; ++q) {
-      (void)hipEventDestroy(s->ev.begin[q]);
-      (void)hipEventDestroy(s->ev.end[q]);
-    }
+    destroy_events(s);
     s->timing = false;
   }
-  s->phase_ms = 0.0;
-  s->phase_launches = 0;
+  s->pending = 0;
+  s->phase_ms = s->count_ms = s->scatter_ms = 0.0;
+  s->phase_launches = s->rebin_launches = 0;
   return EC_OK;
 }
 
 ec_status ec_get_timing(ec_system s, double* phase_ms, int64_t* launches) {
   if (!s || !phase_ms || !launches) return EC_E_INVALID;
+  ec_status st = resolve_timing(s);
+  if (st != EC_OK) return st;
   *phase_ms = s->phase_ms;
   *launches = s->phase_launches;
+  return EC_OK;
+}
+
+ec_status ec_get_rebin_timing(ec_system s, double* count_ms, double* scatter_ms,
+                              int64_t* sweeps) {
+  if (!s || !count_ms || !scatter_ms || !sweeps) return EC_E_INVALID;
+  ec_status st = resolve_timing(s);
+  if (st != EC_OK) return st;
+  *count_ms = s->count_ms;
+  *scatter_ms = s->scatter_ms;
+  *sweeps = s->rebin_launches;
   return EC_OK;
 }
 
@@ -459,14 +578,27 @@ ec_status ec_set_dep_wait_limit(ec_system s, double seconds) {
 static ec_status check_err(ec_system s) {
   int32_t err[2] = {0, 0};
   double dbg[ec::kDebugWords];
+  unsigned long long ovl[4] = {0, 0, 0, 0};
   EC_HIP(s, hipMemcpyAsync(err, s->dev.err, 8, hipMemcpyDeviceToHost, s->stream));
   EC_HIP(s, hipMemcpyAsync(dbg, s->dev.dbg, sizeof dbg, hipMemcpyDeviceToHost, s->stream));
+  EC_HIP(s, hipMemcpyAsync(ovl, s->dev.ovl, sizeof ovl, hipMemcpyDeviceToHost, s->stream));
   EC_HIP(s, hipStreamSynchronize(s->stream));
+  if (err[0] == ec::ERR_OVERLAP) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf,
+                  "overlap check: %llu pairs closer than sigma after sweep %llu; first pair: "
+                  "disks %llu and %llu",
+                  ovl[0], ovl[3], ovl[1], ovl[2]);
+    s->last_error = buf;
+    return EC_E_OVERLAP;
+  }
   if (err[0] != 0) {
     char buf[512];
     std::snprintf(buf, sizeof buf,
                   "device check failed (bits 0x%x: 1 cell capacity, 2 bin capacity, 4 events per "
-                  "chain, 8 draw retries, 16 dependency wait, 32 undo log); first tripped chain: "
+                  "chain, 8 draw retries, 16 dependency wait, 32 undo log, 64 overlap, 128 batch "
+                  "sweep abandoned after another system's error); first "
+                  "tripped chain: "
                   "cell %.0f "
                   "chain %.0f sweep %.0f "
                   "phase %.0f pos (%.17g, %.17g) dir (%.17g, %.17g) rem %.17g slot %.0f id %.0f "
@@ -776,7 +908,7 @@ ec_status ec_get_sweep_count(ec_system s, int64_t* sweeps) {
 ec_status ec_destroy(ec_system s) {
   if (!s) return EC_E_INVALID;
   if (s->in_batch) return EC_E_STATE;  // views are destroyed with their batch
-  if (s->timing) ec_set_timing(s, 0);
+  if (s->timing) (void)ec_set_timing(s, 0);  // cleanup: its failure is reported below
   hipError_t e = hipStreamSynchronize(s->stream);
   delete s;
   return e == hipSuccess ? EC_OK : EC_E_HIP;
@@ -790,6 +922,7 @@ ec_status ec_destroy(ec_system s) {
 struct ec_batch_s {
   std::vector<ec_system> sys;
   std::vector<size_t> off;      // byte offset of each system's region
+  int32_t schedule;             // EC_SCHEDULE_*
   unsigned char* ws;
   size_t sys_bytes;             // bytes of all system regions (snapshot size)
   ec::Dev* devs_d;              // device array of the systems' records
@@ -807,8 +940,10 @@ namespace {
 constexpr int32_t kMaxBatch = 4096;
 
 struct BatchLayout {
-  size_t devs, systems, snapshot, total;
+  size_t devs, q_hdr, q_tasks, q_flags, q_dep, q_base, systems, snapshot, total;
+  int32_t cells;                // cells of all systems (ready-queue slots)
   std::vector<size_t> off;
+  std::vector<int32_t> base;    // first queue index of each system's cells, then the total
 };
 
 ec_status batch_layout(const ec_params* ps, int32_t n, BatchLayout* bl, std::vector<Derived>* dvs,
@@ -817,6 +952,20 @@ ec_status batch_layout(const ec_params* ps, int32_t n, BatchLayout* bl, std::vec
   size_t o = 0;
   bl->devs = o;
   o = align256(o + sizeof(ec::Dev) * (size_t)n);
+  bl->base.assign((size_t)n + 1, 0);
+  int64_t cells = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    bl->base[(size_t)i] = (int32_t)cells;
+    cells += (int64_t)ps[i].cells_per_side * ps[i].cells_per_side;
+    if (cells > (int64_t(1) << 30)) { *why = "too many cells in the batch"; return EC_E_INVALID; }
+  }
+  bl->base[(size_t)n] = (int32_t)cells;
+  bl->cells = (int32_t)cells;
+  bl->q_hdr = o;   o = align256(o + 16);
+  bl->q_tasks = o; o = align256(o + 8 * (size_t)cells);
+  bl->q_flags = o; o = align256(o + 4 * (size_t)cells);
+  bl->q_dep = o;   o = align256(o + 4 * (size_t)cells);
+  bl->q_base = o;  o = align256(o + 4 * ((size_t)n + 1));
   bl->systems = o;
   bl->off.resize((size_t)n);
   dvs->resize((size_t)n);
@@ -827,7 +976,8 @@ ec_status batch_layout(const ec_params* ps, int32_t n, BatchLayout* bl, std::vec
     if (ps[i].precision != ps[0].precision) {
       *why = "the systems of a batch share one precision"; return EC_E_UNSUPPORTED;
     }
-    if ((ps[i].flags ^ ps[0].flags) & (EC_FLAG_PHASE_LAUNCHES | EC_FLAG_ONE_LAUNCH | EC_FLAG_REJECT)) {
+    if ((ps[i].flags ^ ps[0].flags) &
+        (EC_FLAG_PHASE_LAUNCHES | EC_FLAG_ONE_LAUNCH | EC_FLAG_REJECT | EC_FLAG_STRIPES)) {
       *why = "the systems of a batch share one schedule"; return EC_E_UNSUPPORTED;
     }
     bl->off[(size_t)i] = o;
@@ -840,8 +990,30 @@ ec_status batch_layout(const ec_params* ps, int32_t n, BatchLayout* bl, std::vec
   return EC_OK;
 }
 
+// The launch shape of the batch's schedule (ready queue: as many persistent
+// wavefronts as fit on the device, at most one per cell).
+ec_status batch_apply_schedule(ec_batch b) {
+  ec::LaunchShape& sh = b->shape;
+  // (the striped decomposition has its own two phase launches)
+  sh.one_launch = b->schedule == EC_SCHEDULE_ONE_LAUNCH && !sh.stripes;
+  sh.ready_queue = b->schedule == EC_SCHEDULE_READY_QUEUE && !sh.stripes;
+  if (sh.ready_queue) {
+    int workers = 0;
+    hipError_t e = ec::ready_queue_workers(sh.max_lds_per_cell, sh.cpb, sh.fp32_screen ? 1 : 0,
+                                           sh.reject ? 1 : 0, &workers);
+    if (e != hipSuccess) {
+      b->last_error = std::string("ready-queue occupancy: ") + hipGetErrorString(e);
+      return EC_E_HIP;
+    }
+    sh.queue.workers = std::max(1, std::min(workers, sh.queue.total));
+  }
+  return EC_OK;
+}
+
 // Upload the records with the batch's schedule and drop any captured graph.
 ec_status batch_sync_records(ec_batch b) {
+  ec_status st0 = batch_apply_schedule(b);
+  if (st0 != EC_OK) return st0;
   std::vector<ec::Dev> h(b->sys.size());
   for (size_t i = 0; i < b->sys.size(); ++i) {
     b->sys[i]->dev.cells_per_block = b->shape.cpb;
@@ -934,14 +1106,38 @@ ec_status ec_init_batch(const ec_params* ps, int32_t n_sys, void* ws, size_t ws_
   b->stream = (hipStream_t)stream;
   b->use_graph = false;
   b->graph_ready = false;
+  // schedule: the ready queue unless a schedule flag asks for another
+  b->schedule = (ps[0].flags & EC_FLAG_ONE_LAUNCH)       ? EC_SCHEDULE_ONE_LAUNCH
+                : (ps[0].flags & EC_FLAG_PHASE_LAUNCHES) ? EC_SCHEDULE_PHASE_LAUNCHES
+                                                         : EC_SCHEDULE_READY_QUEUE;
   ec::LaunchShape& sh = b->shape;
   std::memset(&sh, 0, sizeof sh);
   sh.n_sys = n_sys;
   sh.periodic = false;
   sh.fp32_screen = ps[0].precision == EC_PREC_FP32_SCREEN;
-  sh.one_launch = (ps[0].flags & EC_FLAG_ONE_LAUNCH) != 0;  // phase launches unless asked
   sh.reject = (ps[0].flags & EC_FLAG_REJECT) != 0;
+  sh.stripes = (ps[0].flags & EC_FLAG_STRIPES) != 0;
   sh.cpb = 1;
+  sh.queue.hdr = (int32_t*)(b->ws + bl.q_hdr);
+  sh.queue.tasks = (int64_t*)(b->ws + bl.q_tasks);
+  sh.queue.flags = (int32_t*)(b->ws + bl.q_flags);
+  sh.queue.dep = (int32_t*)(b->ws + bl.q_dep);
+  sh.queue.base = (const int32_t*)(b->ws + bl.q_base);
+  sh.queue.total = bl.cells;
+  sh.queue.workers = 1;
+  {
+    // queue header, flags and per-system bases (init synchronises below)
+    hipError_t e = hipMemsetAsync(b->ws + bl.q_hdr, 0, 16, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->ws + bl.q_flags, 0, 4 * (size_t)bl.cells, b->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->ws + bl.q_base, bl.base.data(), 4 * bl.base.size(), hipMemcpyHostToDevice,
+                         b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // bl.base is a local
+    if (e != hipSuccess) {
+      delete b;
+      return EC_E_HIP;
+    }
+  }
   for (int32_t i = 0; i < n_sys; ++i) {
     ec_params p = ps[i];
     p.cells_per_block = 1;
@@ -957,9 +1153,11 @@ ec_status ec_init_batch(const ec_params* ps, int32_t n_sys, void* ws, size_t ws_
     b->sys.push_back(s);
     const ec::LaunchShape& one = s->shape;
     sh.any_distinct = sh.any_distinct || one.any_distinct;
+    sh.check_overlap = sh.check_overlap || one.check_overlap;
     sh.max_n = std::max(sh.max_n, one.max_n);
     sh.max_chains = std::max(sh.max_chains, one.max_chains);
     sh.max_cells = std::max(sh.max_cells, one.max_cells);
+    sh.max_cells_side = std::max(sh.max_cells_side, one.max_cells_side);
     sh.max_active = std::max(sh.max_active, one.max_active);
     sh.max_lds_per_cell = std::max(sh.max_lds_per_cell, one.max_lds_per_cell);
   }
@@ -1002,7 +1200,15 @@ ec_status ec_batch_set_cells_per_block(ec_batch b, int32_t cpb) {
   return batch_sync_records(b);
 }
 
-ec_status ec_batch_autotune(ec_batch b, int32_t trial_sweeps, int32_t* cpb_out, double* ms_out) {
+ec_status ec_batch_set_schedule(ec_batch b, int32_t schedule) {
+  if (!b) return EC_E_INVALID;
+  if (schedule < EC_SCHEDULE_PHASE_LAUNCHES || schedule > EC_SCHEDULE_READY_QUEUE) return EC_E_INVALID;
+  b->schedule = schedule;
+  return batch_sync_records(b);
+}
+
+ec_status ec_batch_autotune(ec_batch b, int32_t trial_sweeps, int32_t* schedule_out,
+                            int32_t* cpb_out, double* ms_out) {
   if (!b || trial_sweeps < 1) return EC_E_INVALID;
   // the trials run from a snapshot of every system's state, which is put back
   // afterwards: the schedule changes timing only, never the trajectory
@@ -1016,44 +1222,50 @@ ec_status ec_batch_autotune(ec_batch b, int32_t trial_sweeps, int32_t* cpb_out, 
   if ((e = hipEventCreate(&t0)) != hipSuccess) return batch_fail(b, e, "event");
   if ((e = hipEventCreate(&t1)) != hipSuccess) { (void)hipEventDestroy(t0); return batch_fail(b, e, "event"); }
   const int32_t cands[3] = {1, 2, 4};
-  int32_t best = b->shape.cpb;
+  int32_t best = b->shape.cpb, best_sched = b->schedule;
   double best_ms = 0.0;
   ec_status st = EC_OK;
-  for (int c = 0; c < 3 && st == EC_OK; ++c) {
-    double ms_c = -1.0;
-    if ((size_t)cands[c] * (size_t)b->shape.max_lds_per_cell <= 160 * 1024) {
-      b->shape.cpb = cands[c];
-      st = batch_sync_records(b);
-      if (st != EC_OK) break;
-      e = hipMemcpyAsync(sys0, snap, b->sys_bytes, hipMemcpyDeviceToDevice, b->stream);
-      if (e == hipSuccess) st = batch_sweeps(b, 1);  // warm-up (graph capture, caches)
-      if (e == hipSuccess && st == EC_OK) e = hipMemcpyAsync(sys0, snap, b->sys_bytes, hipMemcpyDeviceToDevice, b->stream);
-      if (e == hipSuccess && st == EC_OK) e = hipEventRecord(t0, b->stream);
-      if (e == hipSuccess && st == EC_OK) st = batch_sweeps(b, trial_sweeps);
-      if (e == hipSuccess && st == EC_OK) e = hipEventRecord(t1, b->stream);
-      if (e == hipSuccess && st == EC_OK) e = hipEventSynchronize(t1);
-      float ms = 0.f;
-      if (e == hipSuccess && st == EC_OK) e = hipEventElapsedTime(&ms, t0, t1);
-      if (e != hipSuccess) { st = batch_fail(b, e, "autotune trial"); break; }
-      ms_c = ms;
-      if (best_ms == 0.0 || ms < best_ms) { best_ms = ms; best = cands[c]; }
+  for (int sc = EC_SCHEDULE_PHASE_LAUNCHES; sc <= EC_SCHEDULE_READY_QUEUE && st == EC_OK; ++sc) {
+    for (int c = 0; c < 3 && st == EC_OK; ++c) {
+      double ms_c = -1.0;
+      if ((size_t)cands[c] * (size_t)b->shape.max_lds_per_cell <= 160 * 1024) {
+        b->schedule = sc;
+        b->shape.cpb = cands[c];
+        st = batch_sync_records(b);
+        if (st != EC_OK) break;
+        e = hipMemcpyAsync(sys0, snap, b->sys_bytes, hipMemcpyDeviceToDevice, b->stream);
+        if (e == hipSuccess) st = batch_sweeps(b, 1);  // warm-up (graph capture, caches)
+        if (e == hipSuccess && st == EC_OK) e = hipMemcpyAsync(sys0, snap, b->sys_bytes, hipMemcpyDeviceToDevice, b->stream);
+        if (e == hipSuccess && st == EC_OK) e = hipEventRecord(t0, b->stream);
+        if (e == hipSuccess && st == EC_OK) st = batch_sweeps(b, trial_sweeps);
+        if (e == hipSuccess && st == EC_OK) e = hipEventRecord(t1, b->stream);
+        if (e == hipSuccess && st == EC_OK) e = hipEventSynchronize(t1);
+        float ms = 0.f;
+        if (e == hipSuccess && st == EC_OK) e = hipEventElapsedTime(&ms, t0, t1);
+        if (e != hipSuccess) { st = batch_fail(b, e, "autotune trial"); break; }
+        ms_c = ms;
+        if (best_ms == 0.0 || ms < best_ms) { best_ms = ms; best = cands[c]; best_sched = sc; }
+      }
+      if (ms_out) ms_out[3 * sc + c] = ms_c;
     }
-    if (ms_out) ms_out[c] = ms_c;
   }
-  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t0);  // cleanup: failures ignored
   (void)hipEventDestroy(t1);
   // back to the snapshot with the chosen schedule
   e = hipMemcpyAsync(sys0, snap, b->sys_bytes, hipMemcpyDeviceToDevice, b->stream);
   if (e != hipSuccess && st == EC_OK) st = batch_fail(b, e, "restore");
   for (size_t i = 0; i < b->sys.size(); ++i) b->sys[i]->sweeps = sweeps0[i];
   b->shape.cpb = best;
+  b->schedule = best_sched;
   ec_status st2 = batch_sync_records(b);
   if (st == EC_OK) st = st2;
   if (cpb_out) *cpb_out = best;
+  if (schedule_out) *schedule_out = best_sched;
   return st;
 }
 
 const char* ec_batch_last_error(ec_batch b) { return b ? b->last_error.c_str() : ""; }
+
 
 ec_status ec_destroy_batch(ec_batch b) {
   if (!b) return EC_E_INVALID;
@@ -1063,7 +1275,7 @@ ec_status ec_destroy_batch(ec_batch b) {
     (void)hipGraphDestroy(b->graph);
   }
   for (auto* s : b->sys) {
-    if (s->timing) { s->in_batch = false; ec_set_timing(s, 0); }
+    if (s->timing) { s->in_batch = false; (void)ec_set_timing(s, 0); }
     delete s;
   }
   delete b;

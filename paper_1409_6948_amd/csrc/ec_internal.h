@@ -10,7 +10,8 @@ namespace ec {
 // order of the four colours, Sec. 3.4 steps 1 and 3).
 struct SweepDraws {
   double sx, sy;
-  int32_t perm[4];
+  int32_t perm;  // colour of phase q in bits 2q, 2q+1
+  int32_t pad;
 };
 
 // Column order of the per-cell counters.
@@ -23,8 +24,25 @@ enum {
   ERR_EVENT_CAP = 4,   // a chain exceeded kMaxEventsPerChain events
   ERR_DRAW_CAP = 8,    // a rejection draw exceeded kMaxDrawTries attempts
   ERR_DEP_WAIT = 16,   // a cell waited longer than dep_wait_ticks for a neighbour of an earlier phase
-  ERR_UNDO_CAP = 32    // rejection variant: a chain made more lifts than the undo log holds
+  ERR_UNDO_CAP = 32,   // rejection variant: a chain made more lifts than the undo log holds
+  ERR_OVERLAP = 64,    // overlap check (debug flag): two disks closer than sigma after a sweep
+  ERR_ABANDONED = 128  // ready-queue batch sweep: left unfinished after another system's error
 };
+
+// Ready queue of the batched sweep (one launch runs every cell of every
+// system of a batch): header words, then per cell of the batch a task slot,
+// its publication flag, and the count of earlier-phase neighbours not yet
+// done.  Laid out by the batch in its workspace.
+struct ReadyQueue {
+  int32_t* hdr;        // [0] tasks claimed, [1] tasks reserved, [2] sweep epoch, [3] abort
+  int64_t* tasks;      // [total] system << 32 | cell, in the order cells became ready
+  int32_t* flags;      // [total] epoch of the sweep that published the slot
+  int32_t* dep;        // [total] earlier-phase neighbours still running or waiting
+  const int32_t* base; // [n_sys + 1] first queue index of each system's cells
+  int32_t total;       // cells of all systems
+  int32_t workers;     // wavefronts of the persistent launch
+};
+enum { QH_READ = 0, QH_RESERVE = 1, QH_EPOCH = 2, QH_ABORT = 3 };
 
 // Events allowed in one chain before the sweep gives up with ERR_EVENT_CAP.
 // Only degenerate input (a closed ring of touching disks, a disk pinned
@@ -79,6 +97,7 @@ struct Dev {
   unsigned long long* gr_counts;    // [kMaxGrBins + 1] pair counts per bin, then pairs < sigma
   int32_t* queue;                   // [1] ticket counter of the one-launch sweep
   int64_t* cell_done;               // [C*C] last sweep + 1 whose write-back the cell has published
+  unsigned long long* ovl;          // [4] overlap check: pairs found, first pair (i, j), its sweep
 
   int64_t n;
   double sigma, sig2, ell, L, half_L, w, cap, b, inv_b, margin;
@@ -91,6 +110,9 @@ struct Dev {
   int32_t search;                   // 0: 4x4-bin window with guard; 1: scan of every slot
   int64_t dep_wait_ticks;           // one-launch sweep: limit of one wait, 100 MHz clock ticks
   int32_t reject;                   // 1: a chain reaching a wall or a frozen disk is undone
+  int32_t check_overlap;            // 1: every sweep ends with a check of all neighbour pairs
+  int32_t stripes;                  // 1: striped decomposition, C stripes of width w, rejection
+  int32_t stripe_cap_own, stripe_cap_frozen, stripe_undo;  // LDS capacities of one stripe
   uint64_t seed;
   uint32_t system;
 };
@@ -100,13 +122,11 @@ struct Dev {
 // then the own-disk tables and one sink slot per lane (a target for the
 // lanes that do not store when one lane writes a position).
 struct CellLds {
-  int32_t off_pos, off_meta, off_mask, off_own_gid, off_own_loc, off_tmp, off_sink, off_pos32, off_undo,
-      bytes;
+  int32_t off_pos, off_meta, off_mask, off_own_gid, off_own_loc, off_tmp, off_sink, off_undo, bytes;
 };
 
-// fp32: also an FP32 copy of every slot's position (the screened form).
 // reject: an undo log of kUndoCap entries (slots and old position, 32 B each).
-__host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own, bool fp32, bool reject) {
+__host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own, bool reject) {
   CellLds l;
   int slots = gridb * gridb * 4;
   int o = 0;
@@ -118,11 +138,16 @@ __host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own, bool 
   l.off_tmp = o;      o += 4 * cap_own;
   o = (o + 15) & ~15;
   l.off_sink = o;     o += 16 * 64;
-  l.off_pos32 = o;    o += fp32 ? 8 * slots : 0;
-  o = (o + 15) & ~15;
   l.off_undo = o;     o += reject ? 32 * kUndoCap : 0;
   l.bytes = (o + 15) & ~15;
   return l;
+}
+
+// LDS of one stripe in the striped-decomposition kernel: own disks (position
+// along and across the stripe, id, and a staging word), frozen disks
+// (along, across, id), and the undo log (disk, old position along).
+__host__ __device__ inline int stripe_lds_bytes(int cap_own, int cap_frozen, int undo) {
+  return 24 * cap_own + 20 * cap_frozen + 16 * undo + 64;
 }
 
 // Largest N the one-periodic-cell kernel keeps in LDS.
@@ -136,10 +161,15 @@ struct LaunchShape {
   bool any_distinct;        // some system uses the distinct-start control
   bool fp32_screen;         // the FP32-screened phase kernel (same for all)
   bool one_launch;          // all four phases in one launch (k_sweep_cells), else one per phase
+  bool ready_queue;         // a batch: every cell of every system in one launch fed by a ready queue
+  ReadyQueue queue;         // (ready_queue only)
   bool reject;              // rejection at the cell boundary (same for all)
+  bool check_overlap;       // some system checks for overlaps after every sweep
+  bool stripes;             // striped decomposition (same for all)
   int64_t max_n;            // disks
   int64_t max_chains;       // chains per sweep
   int32_t max_cells;        // C * C
+  int32_t max_cells_side;   // C (stripes: the number of stripes)
   int32_t max_active;       // C * C / 4
   int32_t cpb;              // simulation cells per workgroup (same for all)
   int32_t max_lds_per_cell; // bytes
@@ -147,8 +177,11 @@ struct LaunchShape {
 
 // Optional HIP events recorded around every phase launch (begin[q], end[q]);
 // the one-launch sweep and the periodic cell use begin[0], end[0] only.
+// rebin[0..1] bracket the count kernel, rebin[2..3] the scatter kernel
+// (walled cells).
 struct PhaseEvents {
   hipEvent_t begin[4], end[4];
+  hipEvent_t rebin[4];
 };
 
 hipError_t launch_lattice(const Dev* ds, int64_t n, int64_t k, double a, hipStream_t st);
@@ -160,6 +193,10 @@ hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
 hipError_t launch_reduce(const Dev* ds, hipStream_t st);
 // Allow the phase kernel up to `bytes` of dynamic LDS per workgroup.
 hipError_t set_phase_lds_limit(int bytes);
+// Wavefronts of the ready-queue launch that fit on the device at once with
+// this much LDS per cell and cells per workgroup (resident workgroups per CU
+// times CUs times cells per workgroup).
+hipError_t ready_queue_workers(int lds_per_cell, int cpb, int fp32, int reject, int* workers);
 hipError_t launch_zero_tallies(const Dev* ds, int32_t n_cells, hipStream_t st);
 // Hexatic order parameter of one system (cutoff neighbours within r_cut,
 // r_cut <= cell side): rebin of the current sweep, per-disk Psi_k, and a
@@ -175,5 +212,9 @@ hipError_t launch_psi6(const Dev* ds, const LaunchShape& sh, double r_cut, hipSt
 hipError_t launch_psi6_delaunay(const Dev* ds, const LaunchShape& sh, double r_search, hipStream_t st);
 hipError_t launch_gr(const Dev* ds, const LaunchShape& sh, double r_max, double delta, int n_bins,
                      hipStream_t st);
+// Debug check after a sweep: every pair of disks in neighbouring cells of the
+// sweep's grid (all pairs for one periodic cell) closer than sigma (1 - 1e-12)
+// is counted in ovl and sets ERR_OVERLAP.  Systems without check_overlap skip it.
+hipError_t launch_check_overlap(const Dev* ds, const LaunchShape& sh, hipStream_t st);
 
 }  // namespace ec

@@ -347,7 +347,7 @@ __device__ __forceinline__ double local_coord(double p, double shift, double ori
 // Start lattice
 // ---------------------------------------------------------------------------
 __global__ void k_lattice(const Dev* __restrict__ ds, int64_t k, double a) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= d.n) return;
   int64_t j = id / k, i = id % k;
@@ -358,21 +358,30 @@ __global__ void k_lattice(const Dev* __restrict__ ds, int64_t k, double a) {
 // ---------------------------------------------------------------------------
 // Rebin: sweep draws, cell of every disk, counting sort by cell
 // ---------------------------------------------------------------------------
-__device__ void decode_perm(uint64_t idx, int32_t* perm) {
-  int32_t avail[4] = {0, 1, 2, 3};
-  const uint64_t fact[4] = {6, 2, 1, 1};
-  int navail = 4;
+// Permutation number idx in [0, 24) decoded in the factorial base: the
+// colour of phase q lands in bits 2q, 2q+1 of the result.  The colours not
+// yet taken are kept in order as 2-bit fields of `avail`.
+__device__ int32_t decode_perm(uint64_t idx) {
+  uint32_t avail = 0 | (1u << 2) | (2u << 4) | (3u << 6);
+  const uint32_t fact[4] = {6, 2, 1, 1};
+  int32_t out = 0;
+  uint32_t r = (uint32_t)idx;
+#pragma unroll
   for (int pos = 0; pos < 4; ++pos) {
-    uint64_t q = idx / fact[pos];
-    idx = idx % fact[pos];
-    perm[pos] = avail[q];
-    for (int t = (int)q; t < navail - 1; ++t) avail[t] = avail[t + 1];
-    navail--;
+    const uint32_t q = r / fact[pos];
+    r = r % fact[pos];
+    out |= (int32_t)(((avail >> (2 * q)) & 3u) << (2 * pos));
+    // drop field q: the fields above it move down by one
+    const uint32_t low = avail & ((1u << (2 * q)) - 1u);
+    avail = low | ((avail >> (2 * q + 2)) << (2 * q));
   }
+  return out;
 }
 
-__global__ void k_prep(const Dev* __restrict__ ds) {
-  const Dev d = ds[blockIdx.y];
+// squares = 0: the sweep's own decomposition (stripes for a striped system);
+// 1: the square cells that the observables' rebin always uses.
+__global__ void k_prep(const Dev* __restrict__ ds, int squares) {
+  const Dev& d = ds[blockIdx.y];
   const int64_t sweep = *d.sweep_ctr;
   int ncell = d.C * d.C;
   for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
@@ -382,9 +391,17 @@ __global__ void k_prep(const Dev* __restrict__ ds) {
   if (threadIdx.x == 0) {
     Stream st(d.seed, kKindSweep, (uint64_t)sweep, (uint64_t)d.system, 0);
     SweepDraws dr;
-    dr.sx = u01(st.next()) * d.w;
-    dr.sy = u01(st.next()) * d.w;
-    decode_perm(draw_index(st, 24), dr.perm);
+    if (d.stripes && !squares) {
+      // stripes: shift across them, and which of the two colours goes first
+      dr.sx = u01(st.next()) * d.w;
+      dr.sy = 0.0;
+      dr.perm = (int32_t)draw_index(st, 2);
+    } else {
+      dr.sx = u01(st.next()) * d.w;
+      dr.sy = u01(st.next()) * d.w;
+      dr.perm = decode_perm(draw_index(st, 24));
+    }
+    dr.pad = 0;
     *d.draws = dr;
     d.digest_ring[sweep % kDigestRing] = 0;
     *d.queue = 0;  // ticket counter of the one-launch sweep
@@ -400,19 +417,28 @@ __device__ __forceinline__ int cell_of_pos(const Dev& d, double px, double py, d
   return cy * d.C + cx;
 }
 
-__global__ void k_count(const Dev* __restrict__ ds) {
-  const Dev d = ds[blockIdx.y];
+__global__ void k_count(const Dev* __restrict__ ds, int squares) {
+  const Dev& d = ds[blockIdx.y];
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   SweepDraws dr = *d.draws;
-  int c = cell_of_pos(d, d.x[i], d.y[i], dr.sx, dr.sy);
+  int c;
+  if (d.stripes && !squares) {
+    // stripe index from the coordinate across the stripes: horizontal stripes
+    // (across = y) on even sweeps, vertical ones (across = x) on odd sweeps
+    const double across = (*d.sweep_ctr & 1) ? d.x[i] : d.y[i];
+    c = (int)floor(shifted(across, dr.sx, d.L) / d.w);
+    if (c > d.C - 1) c = d.C - 1;
+  } else {
+    c = cell_of_pos(d, d.x[i], d.y[i], dr.sx, dr.sy);
+  }
   d.cell_of[i] = c;
   atomicAdd(&d.cell_count[c], 1);
 }
 
 // Exclusive prefix sum of the cell counts, one workgroup of 1024 threads.
 __global__ void __launch_bounds__(1024) k_scan(const Dev* __restrict__ ds) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   __shared__ int32_t part[1024];
   int ncell = d.C * d.C;
   int per = (ncell + 1023) / 1024;
@@ -436,7 +462,7 @@ __global__ void __launch_bounds__(1024) k_scan(const Dev* __restrict__ ds) {
 }
 
 __global__ void k_scatter(const Dev* __restrict__ ds) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   int c = d.cell_of[i];
@@ -504,7 +530,7 @@ __device__ __forceinline__ int cell_of_slot(const Dev& d, int64_t i) {
 }
 
 __global__ void k_draws(const Dev* __restrict__ ds) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   const int64_t sweep = *d.sweep_ctr;
   const int64_t total = d.chains_per_cell > 0 ? (int64_t)d.C * d.C * d.chains_per_cell : d.n;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -536,7 +562,7 @@ __global__ void k_draws(const Dev* __restrict__ ds) {
 // Distinct-start negative control: one thread per cell shuffles [0, n_c)
 // (Fisher-Yates) and chain k starts at list[k mod n_c].
 __global__ void k_shuffle(const Dev* __restrict__ ds) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   if (d.start_mode != 1) return;
   const int64_t sweep = *d.sweep_ctr;
   int cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -581,7 +607,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
                                            const int q, const int blk, unsigned char* const base,
                                            const int lane) {
   const int half = d.C >> 1;
-  const int colour = dr.perm[q & 3];
+  const int colour = (dr.perm >> (2 * (q & 3))) & 3;
   const int cx = 2 * (blk % half) + (colour & 1);
   const int cy = 2 * (blk / half) + (colour >> 1);
   const int cell = cy * d.C + cx;
@@ -590,7 +616,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
   const int gridb = d.gridb, nb = d.nb;
   const int nslots = gridb * gridb * 4;
 
-  const CellLds lay = cell_lds_layout(gridb, d.cap_own, PREC == 1, REJ == 1);
+  const CellLds lay = cell_lds_layout(gridb, d.cap_own, REJ == 1);
   double2* pos = (double2*)(base + lay.off_pos);
   uint64_t* meta = (uint64_t*)(base + lay.off_meta);
   int32_t* mask = (int32_t*)(base + lay.off_mask);
@@ -600,11 +626,9 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
   // per-lane sink slots: lanes other than 0 write here when lane 0 stores the
   // moved disk, so the store needs no change of the execution mask
   double2* const sink = (double2*)(base + lay.off_sink) + lane;
-  float2* pos32 = (float2*)(base + lay.off_pos32);  // PREC 1 only
   // REJ 1 only: per logged lift the old position, then (slot before, slot after)
   double2* undo_pos = (double2*)(base + lay.off_undo);
   int2* undo_slot = (int2*)(undo_pos + kUndoCap);
-  float2* const sink32 = (float2*)sink;
 
   // ---- stage: own disks, sorted by id -----------------------------------
   const int start = d.cell_start[cell];
@@ -623,8 +647,6 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
   }
   const double2 nan2 = make_double2(__builtin_nan(""), __builtin_nan(""));
   for (int s = lane; s < nslots; s += 64) pos[s] = nan2;
-  if (PREC == 1)
-    for (int s = lane; s < nslots; s += 64) pos32[s] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
   for (int bi = lane; bi < gridb * gridb; bi += 64) mask[bi] = 0;
   wave_sync();
 
@@ -641,7 +663,6 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     if (slot >= 4) { atomicOr(d.err, ERR_BIN_CAP); continue; }
     int s = bin * 4 + slot;
     pos[s] = make_double2(vx, vy);
-    if (PREC == 1) pos32[s] = make_float2((float)vx, (float)vy);
     meta[s] = ((uint64_t)(uint32_t)k << 32) | (uint32_t)g;
     own_loc[k] = s;
   }
@@ -669,7 +690,6 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         if (slot >= 4) { atomicOr(d.err, ERR_BIN_CAP); continue; }
         int s = bin * 4 + slot;
         pos[s] = make_double2(vx, vy);
-        if (PREC == 1) pos32[s] = make_float2((float)vx, (float)vy);
         meta[s] = (0xFFFFFFFFull << 32) | ((uint32_t)g | kFrozenBit);
       }
     }
@@ -691,6 +711,9 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
   int n_ring = 0;            // event records held in the lanes (lane k: record k)
   uint64_t ring_first = 0;    // digest index of record 0
   uint32_t rec_lo = 0, rec_hi = 0, rec_tag = 0;
+  // lane = ks + 4 lx + 16 ly: the four slots of a bin in neighbouring lanes,
+  // so the 16 lanes of one window row read 256 contiguous bytes (no LDS bank
+  // conflicts between rows)
   const int lx = lane & 3, ly = (lane >> 2) & 3, ks = lane >> 4;
   const int loff = ((ly * gridb) + lx) * 4 + ks;  // this lane's slot inside a window
   const double inv_b = d.inv_b;
@@ -810,8 +833,8 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         // FP64 one drop out when they cannot be the minimum; the rest (the
         // survivors) get the FP64 distance.  The minimum over the survivors
         // is then the FP64 minimum over the window.
-        const float2 q32 = pos32[wbase + loff];
-        const float rx = q32.x - (float)ax, ry = q32.y - (float)ay;
+        // the FP32 coordinates are those of the FP64 slot position, rounded
+        const float rx = (float)p.x - (float)ax, ry = (float)p.y - (float)ay;
         const float dx32 = (float)dx, dy32 = (float)dy;
         const float a32 = fmaf(rx, dx32, ry * dy32);
         const float c32 = fmaf(rx, dy32, -(ry * dx32));
@@ -913,10 +936,6 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         {
           double2* const dst = (lane == 0) ? pos + a_loc : sink;
           *dst = make_double2(nax, nay);
-          if (PREC == 1) {
-            float2* const dst32 = (lane == 0) ? pos32 + a_loc : sink32;
-            *dst32 = make_float2((float)nax, (float)nay);
-          }
         }
         __builtin_amdgcn_wave_barrier();
         if (__builtin_expect(++n_ring == kDigestBatch, 0)) {
@@ -1050,10 +1069,6 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       if (nbx == abx && nby == aby) {
         double2* const dst = (lane == 0) ? pos + a_loc : sink;
         *dst = make_double2(ax, ay);
-        if (PREC == 1) {
-          float2* const dst32 = (lane == 0) ? pos32 + a_loc : sink32;
-          *dst32 = make_float2((float)ax, (float)ay);
-        }
       } else {
         const int abin = aby * gridb + abx, nbin = nby * gridb + nbx;
         const int nm = uniform_i32(mask[nbin]);
@@ -1062,7 +1077,6 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
           if (lane == 0) {
             atomicOr(d.err, ERR_BIN_CAP);
             pos[a_loc] = make_double2(ax, ay);
-            if (PREC == 1) pos32[a_loc] = make_float2((float)ax, (float)ay);
           }
         } else {
           const int ns = nbin * 4 + free_slot;
@@ -1071,10 +1085,6 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
             pos[a_loc] = nan2;
             mask[nbin] = nm | (1 << free_slot);
             pos[ns] = make_double2(ax, ay);
-            if (PREC == 1) {
-              pos32[a_loc] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
-              pos32[ns] = make_float2((float)ax, (float)ay);
-            }
             meta[ns] = ((uint64_t)(uint32_t)a_lidx << 32) | a_gid;
             own_loc[a_lidx] = ns;
           }
@@ -1207,7 +1217,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
 // cell; the launch boundary separates the phases.
 template <int PREC, int REJ>
 __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   const int64_t sweep = *d.sweep_ctr;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int lane = threadIdx.x & 63;
@@ -1238,7 +1248,7 @@ __global__ void __launch_bounds__(256) k_phase(const Dev* __restrict__ ds, int q
 // error and leaves, and the sweep reports it.
 template <int PREC, int REJ>
 __global__ void __launch_bounds__(256) k_sweep_cells(const Dev* __restrict__ ds) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   const int64_t sweep = *d.sweep_ctr;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int lane = threadIdx.x & 63;
@@ -1252,7 +1262,7 @@ __global__ void __launch_bounds__(256) k_sweep_cells(const Dev* __restrict__ ds)
   const int64_t epoch = sweep + 1;
   // phase of each colour, two bits per colour
   int phase_of = 0;
-  for (int q = 0; q < 4; ++q) phase_of |= q << (2 * (dr.perm[q] & 3));
+  for (int q = 0; q < 4; ++q) phase_of |= q << (2 * ((dr.perm >> (2 * q)) & 3));
 
   for (;;) {
     int t = 0;
@@ -1261,7 +1271,7 @@ __global__ void __launch_bounds__(256) k_sweep_cells(const Dev* __restrict__ ds)
     if (t >= 4 * per_phase) break;
     const int q = t / per_phase;
     const int blk = t - q * per_phase;
-    const int colour = dr.perm[q];
+    const int colour = (dr.perm >> (2 * q)) & 3;
     const int cx = 2 * (blk % half) + (colour & 1);
     const int cy = 2 * (blk / half) + (colour >> 1);
     if (q > 0) {
@@ -1308,11 +1318,360 @@ __global__ void __launch_bounds__(256) k_sweep_cells(const Dev* __restrict__ ds)
 }
 
 // ---------------------------------------------------------------------------
+// Batched sweep with a ready queue: one launch runs every cell of every
+// system of a batch.  A cell is ready once its earlier-phase neighbours in its
+// own system are done (the only order the colour phases impose, Sec. 3.4 step
+// 4); ready cells are appended to a queue, and persistent wavefronts take
+// them in order, so no wavefront holds a slot while it waits for a
+// neighbour, and no system waits for the slowest cell of another.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int cell_phase(int phase_of, int C, int cell) {
+  const int cx = cell % C, cy = cell / C;
+  return (phase_of >> (2 * ((cx & 1) | ((cy & 1) << 1)))) & 3;
+}
+__device__ __forceinline__ int phase_map(int perm) {  // phase of each colour, two bits per colour
+  int phase_of = 0;
+  for (int q = 0; q < 4; ++q) phase_of |= q << (2 * ((perm >> (2 * q)) & 3));
+  return phase_of;
+}
+
+__device__ __forceinline__ void queue_push(const ReadyQueue& rq, int32_t epoch, int64_t task) {
+  const int r = atomicAdd(rq.hdr + QH_RESERVE, 1);
+  rq.tasks[r] = task;
+  // the task word before its flag
+  __hip_atomic_store(rq.flags + r, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// New sweep: counters cleared, epoch advanced (one thread).
+__global__ void k_queue_reset(ReadyQueue rq) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    rq.hdr[QH_READ] = 0;
+    rq.hdr[QH_RESERVE] = 0;
+    rq.hdr[QH_EPOCH] += 1;
+    rq.hdr[QH_ABORT] = 0;
+  }
+}
+
+// Count every cell's earlier-phase neighbours; cells with none (the first
+// phase) are ready at once.  One thread per cell, grid y = system.
+__global__ void k_queue_prep(const Dev* __restrict__ ds, ReadyQueue rq) {
+  const Dev& d = ds[blockIdx.y];
+  const int ncell = d.C * d.C;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int phase_of = phase_map(d.draws->perm);
+  const int q = cell_phase(phase_of, d.C, c);
+  const int cx = c % d.C, cy = c / d.C;
+  int n = 0;
+  for (int k = 0; k < 9; ++k) {
+    if (k == 4) continue;
+    const int nc = ((cy + k / 3 - 1 + d.C) % d.C) * d.C + (cx + k % 3 - 1 + d.C) % d.C;
+    n += cell_phase(phase_of, d.C, nc) < q ? 1 : 0;
+  }
+  const int g = rq.base[blockIdx.y] + c;
+  rq.dep[g] = n;
+  if (n == 0) queue_push(rq, rq.hdr[QH_EPOCH], ((int64_t)blockIdx.y << 32) | (uint32_t)c);
+}
+
+// Persistent wavefronts: take the next queue slot, wait until it is
+// published, run that cell, then count it off at its later-phase neighbours
+// and append those that become ready.  Every slot below the cell total is
+// published eventually: if every wave waited, every published cell would be
+// done, and the not-done cell of smallest phase would have all its
+// earlier-phase neighbours done, hence be published -- a contradiction.  Each
+// wait is also bounded (the first system's dep_wait_ticks) and given up once
+// any wave has flagged an abort.
+template <int PREC, int REJ>
+__global__ void __launch_bounds__(256) k_queue_cells(const Dev* __restrict__ ds, ReadyQueue rq,
+                                                     int lds_stride) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  // the waves of a workgroup take cells of any system: regions of the largest size
+  unsigned char* const base = lds_raw + (size_t)wave * lds_stride;
+  const int32_t epoch = __hip_atomic_load(rq.hdr + QH_EPOCH, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t limit = (uint64_t)ds[0].dep_wait_ticks;
+  for (;;) {
+    int t = 0;
+    if (lane == 0) t = atomicAdd(rq.hdr + QH_READ, 1);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if (t >= rq.total) break;
+    const uint64_t t0 = wall_clock64();
+    bool ok = true;
+    for (;;) {
+      int f = 0, ab = 0;
+      if (lane == 0) {
+        f = __hip_atomic_load(rq.flags + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ab = __hip_atomic_load(rq.hdr + QH_ABORT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      f = __builtin_amdgcn_readfirstlane(f);
+      ab = __builtin_amdgcn_readfirstlane(ab);
+      if (f == epoch) break;
+      if (ab != 0) { ok = false; break; }
+      if (wall_clock64() - t0 >= limit) {
+        if (lane == 0) {
+          atomicOr(ds[0].err, ERR_DEP_WAIT);
+          atomicExch(rq.hdr + QH_ABORT, 1);
+        }
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(4);
+    }
+    if (!ok) break;
+    // the slot, and the write-backs of the cell's earlier-phase neighbours,
+    // are visible to the loads below
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int64_t task = rq.tasks[t];
+    const int sys = (int)(task >> 32), cell = (int)(uint32_t)task;
+    const Dev& d = ds[sys];
+    const int64_t sweep = *d.sweep_ctr;
+    const SweepDraws dr = *d.draws;
+    const int phase_of = phase_map(dr.perm);
+    const int q = cell_phase(phase_of, d.C, cell);
+    const int cx = cell % d.C, cy = cell / d.C;
+    const int blk = (cy >> 1) * (d.C >> 1) + (cx >> 1);
+    phase_cell<PREC, REJ>(d, sweep, dr, q, blk, base, lane);
+    if (__builtin_amdgcn_readfirstlane(load_err(d)) != 0) {
+      if (lane == 0) atomicExch(rq.hdr + QH_ABORT, 1);
+      break;
+    }
+    // this cell's write-back before its neighbours count it off
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane < 8) {
+      const int k = lane < 4 ? lane : lane + 1;  // the 3 x 3 block without its centre
+      const int nc = ((cy + k / 3 - 1 + d.C) % d.C) * d.C + (cx + k % 3 - 1 + d.C) % d.C;
+      if (cell_phase(phase_of, d.C, nc) > q) {
+        const int g = rq.base[sys] + nc;
+        const int left = __hip_atomic_fetch_add(rq.dep + g, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (left == 1) queue_push(rq, epoch, ((int64_t)sys << 32) | (uint32_t)nc);
+      }
+    }
+    wave_sync();  // LDS reads of this cell before the next cell's staging writes
+  }
+}
+
+// After the launch: if a wave gave up (an error in some system, or a wait
+// limit), mark every system of the batch, since their sweeps are unfinished.
+__global__ void k_queue_check(const Dev* __restrict__ ds, ReadyQueue rq) {
+  const Dev& d = ds[blockIdx.y];
+  if (threadIdx.x == 0 && rq.hdr[QH_ABORT] != 0) atomicOr(d.err, ERR_ABANDONED);
+}
+
+// ---------------------------------------------------------------------------
+// Striped decomposition with rejection (Sec. 3.4, Fig. 3 "stripes"; Sec. 4):
+// C stripes of width w span the box; on even sweeps they are horizontal and
+// chains run along x, on odd sweeps vertical with chains along y, each chain
+// with a random sign (a chain and its reverse are proposed alike, and a chain
+// is rejected exactly when its reverse is).  Colour phase q runs every stripe
+// k with (k & 1) == first ^ q, one wavefront each; a chain that hits a disk
+// of a neighbouring stripe is rejected and undone.
+// The search is a brute-force minimum over the stripe's disks and the frozen
+// disks of its two neighbours within sigma of it (nearest image along the
+// stripe, flights capped at L/2 - sigma as in one periodic box).
+// ---------------------------------------------------------------------------
+template <int DUMMY>
+__global__ void __launch_bounds__(64) k_stripe_phase(const Dev* __restrict__ ds, int q) {
+  const Dev& d = ds[blockIdx.y];
+  const int64_t sweep = *d.sweep_ctr;
+  const SweepDraws dr = *d.draws;
+  const int k = 2 * (int)blockIdx.x + ((dr.perm ^ q) & 1);
+  if (k >= d.C) return;  // the whole wave leaves
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int lane = threadIdx.x;
+  const int cap_own = d.stripe_cap_own, cap_fr = d.stripe_cap_frozen, cap_undo = d.stripe_undo;
+  double* own_a = (double*)lds_raw;
+  double* own_v = own_a + cap_own;
+  double* fr_a = own_v + cap_own;
+  double* fr_v = fr_a + cap_fr;
+  double* undo_a = fr_v + cap_fr;
+  int32_t* own_gid = (int32_t*)(undo_a + cap_undo);
+  int32_t* tmp = own_gid + cap_own;
+  int32_t* fr_gid = tmp + cap_own;
+  int32_t* undo_i = fr_gid + cap_fr;
+  int32_t* n_fr_sh = undo_i + cap_undo;
+
+  double* const along = (sweep & 1) ? d.y : d.x;
+  const double* const across = (sweep & 1) ? d.x : d.y;
+  const double L = d.L, half_L = d.half_L, sigma = d.sigma, sig2 = d.sig2, cap = d.cap;
+  const double origin = (double)k * d.w;
+
+  // ---- stage: own disks in id order, frozen disks of the two neighbours
+  const int start = d.cell_start[k];
+  const int n_own = d.cell_start[k + 1] - start;
+  if (n_own < 0 || n_own > cap_own) {
+    if (lane == 0) atomicOr(d.err, ERR_OWN_CAP);
+    return;
+  }
+  for (int i = lane; i < n_own; i += 64) tmp[i] = d.cell_ids[start + i];
+  if (lane == 0) *n_fr_sh = 0;
+  wave_sync();
+  for (int i = lane; i < n_own; i += 64) {
+    const int v = tmp[i];
+    int r = 0;
+    for (int j = 0; j < n_own; ++j) r += (tmp[j] < v) ? 1 : 0;
+    own_gid[r] = v;
+  }
+  wave_sync();
+  for (int i = lane; i < n_own; i += 64) {
+    const int g = own_gid[i];
+    own_a[i] = along[g];
+    own_v[i] = local_coord(across[g], dr.sx, origin, L, half_L);
+  }
+  for (int side = -1; side <= 1; side += 2) {
+    const int nk = (k + side + d.C) % d.C;
+    const int s0 = d.cell_start[nk], s1 = d.cell_start[nk + 1];
+    for (int t = s0 + lane; t < s1; t += 64) {
+      const int g = d.cell_ids[t];
+      const double v = local_coord(across[g], dr.sx, origin, L, half_L);
+      if (v >= -sigma && v <= d.w + sigma) {
+        const int slot = atomicAdd(n_fr_sh, 1);
+        if (slot < cap_fr) {
+          fr_a[slot] = along[g];
+          fr_v[slot] = v;
+          fr_gid[slot] = g;
+        } else {
+          atomicOr(d.err, ERR_OWN_CAP);
+        }
+      }
+    }
+  }
+  wave_sync();
+  const int n_fr = min(*n_fr_sh, cap_fr);
+  if (__builtin_amdgcn_readfirstlane(load_err(d)) != 0) return;
+
+  // ---- chains
+  const int64_t n_m = chains_of(d, n_own);
+  const int64_t cbase = chain_base(d, k);
+  double acc = d.acc_delta[k];
+  uint64_t n_lift = 0, n_frozen = 0, n_pseudo = 0, h = 0, n_ev = 0;
+  bool stop = false;
+  for (int64_t c = 0; c < n_m && !stop; ++c) {
+    int a = uniform_i32(d.chain_start[cbase + c]);
+    if (a < 0 || a >= n_own) a = 0;  // guarded: the draw kernel writes indices below n_own
+    // the chain's sign: the top bit of the first word of its direction stream
+    Stream ss(d.seed, kKindDir, (uint64_t)sweep, cell_key(d, k), (uint64_t)c);
+    const bool neg = (ss.next() >> 63) != 0;
+    double rem = d.ell, chain_acc = 0.0;
+    uint64_t chain_lifts = 0;
+    int n_undo = 0;
+    int64_t events = 0;
+    for (;;) {
+      if (++events > kMaxEventsPerChain || (events % kAbortPollEvents) == 0) {
+        if (events > kMaxEventsPerChain) {
+          if (lane == 0) atomicOr(d.err, ERR_EVENT_CAP);
+          stop = true;
+          break;
+        }
+        if (uniform_i32(load_err(d)) != 0) { stop = true; break; }
+      }
+      const double aa = own_a[a], av = own_v[a];
+      double ls = INFINITY;
+      uint32_t lid = 0xFFFFFFFFu;
+      int lj = -1;  // own index, or cap_own + frozen index
+      for (int j = lane; j < n_own + n_fr; j += 64) {
+        if (j == a) continue;
+        const bool own = j < n_own;
+        const int f = j - n_own;
+        double ra = (own ? own_a[j] : fr_a[f]) - aa;
+        if (ra < -half_L) ra += L; else if (ra >= half_L) ra -= L;
+        if (neg) ra = -ra;
+        const double rv = (own ? own_v[j] : fr_v[f]) - av;
+        const double disc = fma(-rv, rv, sig2);
+        if (ra > 0.0 && disc > 0.0) {
+          double s = ra - sqrt(disc);
+          if (s < 0.0) s = 0.0;
+          const uint32_t gid = (uint32_t)(own ? own_gid[j] : fr_gid[f]);
+          if (s < ls || (s == ls && gid < lid)) { ls = s; lid = gid; lj = j; }
+        }
+      }
+      const int wl = wave_argmin(ls, lid, lj >= 0);
+      double best_s = INFINITY;
+      int bj = -1;
+      uint32_t bgid = 0;
+      if (wl >= 0) {
+        best_s = readlane_f64(ls, wl);
+        bj = readlane_i32(lj, wl);
+        bgid = (uint32_t)readlane_i32((int)lid, wl);
+      }
+      const double lim = best_s < rem ? best_s : rem;
+      if (lim > cap) {
+        // a free flight beyond the nearest-image range: moved in pieces
+        h ^= digest_term(EV_PSEUDO, (uint64_t)d.n + 2, cap, n_ev++);
+        if (n_undo == cap_undo) {
+          if (lane == 0) atomicOr(d.err, ERR_UNDO_CAP);
+          stop = true;
+          break;
+        }
+        if (lane == 0) { undo_i[n_undo] = a; undo_a[n_undo] = aa; }
+        n_undo += 1;
+        double na = neg ? aa - cap : aa + cap;
+        if (na >= L) na -= L; else if (na < 0.0) na += L;
+        if (lane == 0) own_a[a] = na;
+        wave_sync();
+        rem = rem - cap;
+        n_pseudo += 1;
+        continue;
+      }
+      if (!(best_s < rem)) {
+        h ^= digest_term(EV_END, (uint64_t)d.n + 3, rem, n_ev++);
+        double na = neg ? aa - rem : aa + rem;
+        if (na >= L) na -= L; else if (na < 0.0) na += L;
+        if (lane == 0) own_a[a] = na;
+        wave_sync();
+        acc = acc + chain_acc;  // accepted
+        n_lift += chain_lifts;
+        break;
+      }
+      const bool frozen = bj >= n_own;
+      h ^= digest_term(frozen ? EV_FROZEN : EV_LIFT, bgid, best_s, n_ev++);
+      if (n_undo == cap_undo) {
+        if (lane == 0) atomicOr(d.err, ERR_UNDO_CAP);
+        stop = true;
+        break;
+      }
+      if (lane == 0) { undo_i[n_undo] = a; undo_a[n_undo] = aa; }
+      n_undo += 1;
+      double na = neg ? aa - best_s : aa + best_s;
+      if (na >= L) na -= L; else if (na < 0.0) na += L;
+      if (lane == 0) own_a[a] = na;
+      wave_sync();
+      rem = rem - best_s;
+      if (frozen) {
+        // a disk of a neighbouring stripe: the chain is rejected and undone
+        n_frozen += 1;
+        if (lane == 0)
+          for (int u = n_undo - 1; u >= 0; --u) own_a[undo_i[u]] = undo_a[u];
+        wave_sync();
+        break;
+      }
+      double r = own_a[bj] - na;
+      if (r < -half_L) r += L; else if (r >= half_L) r -= L;
+      chain_acc = chain_acc + (neg ? -r : r);
+      chain_lifts += 1;
+      a = bj;
+    }
+  }
+  wave_sync();
+  for (int i = lane; i < n_own; i += 64) along[own_gid[i]] = own_a[i];
+  if (lane == 0) {
+    d.acc_delta[k] = acc;
+    unsigned long long* cn = d.acc_cnt + (size_t)k * CNT_NCOL;
+    cn[CNT_LIFTS] += n_lift;
+    cn[CNT_FROZEN] += n_frozen;
+    cn[CNT_CHAINS] += (uint64_t)n_m;
+    cn[CNT_PSEUDO] += n_pseudo;
+    d.cell_digest[k] = h;
+    atomicAdd(&d.digest_ring[sweep % kDigestRing], h * (2ull * (uint64_t)k + 1ull));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // One periodic cell (C = 1): all N disks in LDS, brute-force search with the
 // minimum image; flights longer than L/2 - sigma are split (free-flight cap).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) k_periodic(const Dev* __restrict__ ds) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   const int64_t sweep = *d.sweep_ctr;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int lane = threadIdx.x;
@@ -1420,7 +1779,7 @@ __global__ void __launch_bounds__(64) k_periodic(const Dev* __restrict__ ds) {
 // Tallies
 // ---------------------------------------------------------------------------
 __global__ void k_reduce(const Dev* __restrict__ ds) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int ncell = d.C * d.C;
   double s = 0.0;
@@ -1434,7 +1793,7 @@ __global__ void k_reduce(const Dev* __restrict__ ds) {
 }
 
 __global__ void k_zero_tallies(const Dev* __restrict__ ds) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   int ncell = d.C * d.C;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += gridDim.x * blockDim.x) {
     d.acc_delta[i] = 0.0;
@@ -1468,13 +1827,28 @@ hipError_t launch_zero_tallies(const Dev* ds, int32_t n_cells, hipStream_t st) {
 }
 
 hipError_t set_phase_lds_limit(int bytes) {
-  const void* fns[6] = {(const void*)k_phase<0, 0>,       (const void*)k_phase<1, 0>,
-                        (const void*)k_phase<0, 1>,       (const void*)k_sweep_cells<0, 0>,
-                        (const void*)k_sweep_cells<1, 0>, (const void*)k_sweep_cells<0, 1>};
+  const void* fns[10] = {(const void*)k_phase<0, 0>,       (const void*)k_phase<1, 0>,
+                         (const void*)k_phase<0, 1>,       (const void*)k_sweep_cells<0, 0>,
+                         (const void*)k_sweep_cells<1, 0>, (const void*)k_sweep_cells<0, 1>,
+                         (const void*)k_queue_cells<0, 0>, (const void*)k_queue_cells<1, 0>,
+                         (const void*)k_queue_cells<0, 1>, (const void*)k_stripe_phase<0>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+hipError_t ready_queue_workers(int lds_per_cell, int cpb, int fp32, int reject, int* workers) {
+  const void* f = fp32 ? (const void*)k_queue_cells<1, 0>
+                       : (reject ? (const void*)k_queue_cells<0, 1> : (const void*)k_queue_cells<0, 0>);
+  int per_cu = 0, dev = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * cpb,
+                                                              (size_t)cpb * lds_per_cell);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  *workers = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1) * cpb;
   return hipSuccess;
 }
 
@@ -1491,22 +1865,65 @@ hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
     if (ev) (void)hipEventRecord(ev->begin[0], st);
     hipLaunchKernelGGL(k_periodic, dim3(1, ns), dim3(64), lds, st, ds);
     if (ev) (void)hipEventRecord(ev->end[0], st);
+    hipError_t e = launch_check_overlap(ds, sh, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sweep_done, dim3(1, ns), dim3(64), 0, st, ds);
     return hipGetLastError();
   }
   const unsigned nblk = (unsigned)((sh.max_n + 255) / 256);
-  hipLaunchKernelGGL(k_prep, dim3(1, ns), dim3(1024), 0, st, ds);
-  hipLaunchKernelGGL(k_count, dim3(nblk, ns), dim3(256), 0, st, ds);
+  hipLaunchKernelGGL(k_prep, dim3(1, ns), dim3(1024), 0, st, ds, 0);
+  if (ev) (void)hipEventRecord(ev->rebin[0], st);
+  hipLaunchKernelGGL(k_count, dim3(nblk, ns), dim3(256), 0, st, ds, 0);
+  if (ev) (void)hipEventRecord(ev->rebin[1], st);
   hipLaunchKernelGGL(k_scan, dim3(1, ns), dim3(1024), 0, st, ds);
+  if (ev) (void)hipEventRecord(ev->rebin[2], st);
   hipLaunchKernelGGL(k_scatter, dim3(nblk, ns), dim3(256), 0, st, ds);
+  if (ev) (void)hipEventRecord(ev->rebin[3], st);
   hipLaunchKernelGGL(k_draws, dim3((unsigned)((sh.max_chains + 255) / 256), ns), dim3(256), 0, st,
                      ds);
   if (sh.any_distinct)
     hipLaunchKernelGGL(k_shuffle, dim3((unsigned)((sh.max_cells + 63) / 64), ns), dim3(64), 0, st,
                        ds);
+  if (sh.stripes) {
+    // two colour phases of C/2 stripes each, one wavefront per stripe
+    const unsigned sgrid = (unsigned)((sh.max_cells_side + 1) / 2);
+    for (int q = 0; q < 2; ++q) {
+      if (ev) (void)hipEventRecord(ev->begin[q], st);
+      hipLaunchKernelGGL(k_stripe_phase<0>, dim3(sgrid, ns), dim3(64), (size_t)sh.max_lds_per_cell, st,
+                         ds, q);
+      if (ev) (void)hipEventRecord(ev->end[q], st);
+    }
+    hipError_t e = launch_check_overlap(ds, sh, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sweep_done, dim3(1, ns), dim3(64), 0, st, ds);
+    return hipGetLastError();
+  }
   const int cpb = sh.cpb;
   const unsigned grid = (unsigned)((sh.max_active + cpb - 1) / cpb);
   const size_t lds = (size_t)cpb * sh.max_lds_per_cell;
+  if (sh.ready_queue) {
+    const ReadyQueue& rq = sh.queue;
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, rq);
+    hipLaunchKernelGGL(k_queue_prep, dim3((unsigned)((sh.max_cells + 255) / 256), ns), dim3(256), 0,
+                       st, ds, rq);
+    const unsigned qgrid = (unsigned)((rq.workers + cpb - 1) / cpb);
+    if (ev) (void)hipEventRecord(ev->begin[0], st);
+    if (sh.fp32_screen)
+      hipLaunchKernelGGL((k_queue_cells<1, 0>), dim3(qgrid), dim3(64 * cpb), lds, st, ds, rq,
+                         sh.max_lds_per_cell);
+    else if (sh.reject)
+      hipLaunchKernelGGL((k_queue_cells<0, 1>), dim3(qgrid), dim3(64 * cpb), lds, st, ds, rq,
+                         sh.max_lds_per_cell);
+    else
+      hipLaunchKernelGGL((k_queue_cells<0, 0>), dim3(qgrid), dim3(64 * cpb), lds, st, ds, rq,
+                         sh.max_lds_per_cell);
+    if (ev) (void)hipEventRecord(ev->end[0], st);
+    hipLaunchKernelGGL(k_queue_check, dim3(1, ns), dim3(64), 0, st, ds, rq);
+    hipError_t e = launch_check_overlap(ds, sh, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sweep_done, dim3(1, ns), dim3(64), 0, st, ds);
+    return hipGetLastError();
+  }
   if (sh.one_launch) {
     // as many wavefronts as one phase has cells; each takes cells of all phases
     if (ev) (void)hipEventRecord(ev->begin[0], st);
@@ -1517,6 +1934,8 @@ hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
     else
       hipLaunchKernelGGL((k_sweep_cells<0, 0>), dim3(grid, ns), dim3(64 * cpb), lds, st, ds);
     if (ev) (void)hipEventRecord(ev->end[0], st);
+    hipError_t e = launch_check_overlap(ds, sh, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sweep_done, dim3(1, ns), dim3(64), 0, st, ds);
     return hipGetLastError();
   }
@@ -1530,14 +1949,16 @@ hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
       hipLaunchKernelGGL((k_phase<0, 0>), dim3(grid, ns), dim3(64 * cpb), lds, st, ds, q);
     if (ev) (void)hipEventRecord(ev->end[q], st);
   }
+  hipError_t e = launch_check_overlap(ds, sh, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sweep_done, dim3(1, ns), dim3(64), 0, st, ds);
   return hipGetLastError();
 }
 
 hipError_t launch_rebin(const Dev* ds, const LaunchShape& sh, hipStream_t st) {
   const unsigned nblk = (unsigned)((sh.max_n + 255) / 256);
-  hipLaunchKernelGGL(k_prep, dim3(1, 1), dim3(1024), 0, st, ds);
-  hipLaunchKernelGGL(k_count, dim3(nblk, 1), dim3(256), 0, st, ds);
+  hipLaunchKernelGGL(k_prep, dim3(1, 1), dim3(1024), 0, st, ds, 1);
+  hipLaunchKernelGGL(k_count, dim3(nblk, 1), dim3(256), 0, st, ds, 1);
   hipLaunchKernelGGL(k_scan, dim3(1, 1), dim3(1024), 0, st, ds);
   hipLaunchKernelGGL(k_scatter, dim3(nblk, 1), dim3(256), 0, st, ds);
   return hipGetLastError();

@@ -50,7 +50,7 @@ __device__ __forceinline__ void psi6_block_sum(double re, double im, double nb, 
 }
 
 __global__ void __launch_bounds__(256) k_psi6(const Dev* __restrict__ ds, double rc2) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double re = 0.0, im = 0.0;
   int nb = 0;
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(256) k_psi6(const Dev* __restrict__ ds, double
 }
 
 __global__ void __launch_bounds__(1024) k_psi6_final(const Dev* __restrict__ ds, int nblocks) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   __shared__ double sh[3][1024];
   const int t = threadIdx.x;
   double a = 0.0, b = 0.0, c = 0.0;
@@ -192,7 +192,7 @@ __global__ void k_psi6_delaunay_clear(const Dev* __restrict__ ds) {
 
 __global__ void __launch_bounds__(256) k_psi6_delaunay(const Dev* __restrict__ ds, double rs2,
                                                        double vmax2) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   __shared__ double2 cand[4][kMaxCand];
   __shared__ double wsum[4][3];
   const int lane = threadIdx.x & 63;
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(256) k_psi6_delaunay(const Dev* __restrict__ d
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_gr(const Dev* __restrict__ ds, double r_max, double delta,
                                             int n_bins) {
-  const Dev d = ds[blockIdx.y];
+  const Dev& d = ds[blockIdx.y];
   __shared__ unsigned int hist[kMaxGrBins + 1];
   for (int i = threadIdx.x; i <= n_bins; i += blockDim.x) hist[i] = 0;
   __syncthreads();
@@ -337,6 +337,59 @@ __global__ void __launch_bounds__(256) k_gr(const Dev* __restrict__ ds, double r
     if (hist[i]) atomicAdd(&d.gr_counts[i], (unsigned long long)hist[i]);
 }
 
+// ---------------------------------------------------------------------------
+// Overlap check (debug): one thread per disk counts the disks j > i closer
+// than sigma (1 - 1e-12), minimum image, among the 3 x 3 cells of the
+// sweep's grid around its own (a pair closer than sigma < cell side lies in
+// neighbouring cells; disks stay in their cells during a sweep), or among all
+// disks for one periodic cell.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void report_overlap(const Dev& d, int64_t i, int64_t j, int64_t sweep) {
+  if (atomicAdd(d.ovl, 1ull) == 0ull) {
+    d.ovl[1] = (unsigned long long)i;
+    d.ovl[2] = (unsigned long long)j;
+    d.ovl[3] = (unsigned long long)sweep;
+  }
+  atomicOr(d.err, ERR_OVERLAP);
+}
+
+__global__ void __launch_bounds__(256) k_check_overlap(const Dev* __restrict__ ds) {
+  const Dev& d = ds[blockIdx.y];
+  if (!d.check_overlap) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const double L = d.L, half = d.half_L;
+  const double thr = d.sigma * (1.0 - 1e-12), thr2 = thr * thr;
+  const double xi = d.x[i], yi = d.y[i];
+  const int64_t sweep = *d.sweep_ctr;
+  auto test = [&](int64_t j) {
+    if (j <= i) return;
+    double dx = d.x[j] - xi, dy = d.y[j] - yi;
+    if (dx < -half) dx += L; else if (dx >= half) dx -= L;
+    if (dy < -half) dy += L; else if (dy >= half) dy -= L;
+    if (dx * dx + dy * dy < thr2) report_overlap(d, i, j, sweep);
+  };
+  if (d.C == 1) {
+    for (int64_t j = i + 1; j < d.n; ++j) test(j);
+    return;
+  }
+  const int c = d.cell_of[i];
+  if (d.stripes) {  // the sweep's lists are stripes; a pair closer than sigma lies in neighbouring ones
+    for (int side = -1; side <= 1; ++side) {
+      const int nk = (c + side + d.C) % d.C;
+      if (side == 1 && nk == (c - 1 + d.C) % d.C) continue;  // two stripes only
+      for (int t = d.cell_start[nk]; t < d.cell_start[nk + 1]; ++t) test(d.cell_ids[t]);
+    }
+    return;
+  }
+  const int cx = c % d.C, cy = c / d.C;
+  for (int nb = 0; nb < 9; ++nb) {
+    const int ncx = (cx + nb % 3 - 1 + d.C) % d.C, ncy = (cy + nb / 3 - 1 + d.C) % d.C;
+    const int nc = ncy * d.C + ncx;
+    for (int t = d.cell_start[nc]; t < d.cell_start[nc + 1]; ++t) test(d.cell_ids[t]);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_psi6(const Dev* ds, const LaunchShape& sh, double r_cut, hipStream_t st) {
@@ -373,6 +426,13 @@ hipError_t launch_gr(const Dev* ds, const LaunchShape& sh, double r_max, double 
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_gr, dim3(nblk, 1), dim3(256), 0, st, ds, r_max, delta, n_bins);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_overlap(const Dev* ds, const LaunchShape& sh, hipStream_t st) {
+  if (!sh.check_overlap) return hipSuccess;
+  const unsigned nblk = (unsigned)((sh.max_n + 255) / 256);
+  hipLaunchKernelGGL(k_check_overlap, dim3(nblk, (unsigned)sh.n_sys), dim3(256), 0, st, ds);
   return hipGetLastError();
 }
 

@@ -20,6 +20,10 @@ EC_FLAG_SCAN_SEARCH = 1
 EC_FLAG_PHASE_LAUNCHES = 2
 EC_FLAG_ONE_LAUNCH = 4
 EC_FLAG_REJECT = 8
+EC_FLAG_CHECK_OVERLAP = 16
+EC_FLAG_STRIPES = 32
+EC_SCHEDULE_PHASE_LAUNCHES, EC_SCHEDULE_ONE_LAUNCH, EC_SCHEDULE_READY_QUEUE = 0, 1, 2
+SCHEDULE_NAMES = ("phase-launches", "one-launch", "ready-queue")
 EC_ABI_VERSION = 1
 COUNT_NAMES = ("lifts", "frozen", "walls", "chains", "pseudo")
 
@@ -27,10 +31,10 @@ COUNT_NAMES = ("lifts", "frozen", "walls", "chains", "pseudo")
 EXPORTED = ("ec_workspace_bytes", "ec_init_system", "ec_sweep", "ec_measure_pressure",
             "ec_reset_tallies", "ec_get_positions", "ec_set_positions", "ec_get_digests",
             "ec_get_cell_tallies", "ec_get_cell_digests", "ec_get_sweep_count",
-            "ec_set_timing", "ec_get_timing", "ec_set_dep_wait_limit", "ec_destroy", "ec_status_string",
+            "ec_set_timing", "ec_get_timing", "ec_get_rebin_timing", "ec_set_dep_wait_limit", "ec_destroy", "ec_status_string",
             "ec_last_error", "ec_batch_workspace_bytes", "ec_init_batch", "ec_sweep_batch",
             "ec_batch_system", "ec_batch_set_graph", "ec_batch_set_cells_per_block",
-            "ec_batch_autotune", "ec_batch_last_error", "ec_destroy_batch", "ec_measure_psi6",
+            "ec_batch_autotune", "ec_batch_set_schedule", "ec_batch_last_error", "ec_destroy_batch", "ec_measure_psi6",
             "ec_measure_psi6_delaunay", "ec_psi_autocorrelation",
             "ec_gr_accumulate", "ec_gr_counts", "ec_gr_reset", "ec_gr_normalize")
 
@@ -90,6 +94,7 @@ def load_library():
         "ec_get_sweep_count": [vp, C.POINTER(C.c_int64)],
         "ec_set_timing": [vp, C.c_int32],
         "ec_get_timing": [vp, dp, C.POINTER(C.c_int64)],
+        "ec_get_rebin_timing": [vp, dp, dp, C.POINTER(C.c_int64)],
         "ec_set_dep_wait_limit": [vp, C.c_double],
         "ec_destroy": [vp],
         "ec_batch_workspace_bytes": [P, C.c_int32, C.POINTER(C.c_size_t)],
@@ -98,7 +103,8 @@ def load_library():
         "ec_batch_system": [vp, C.c_int32, C.POINTER(vp)],
         "ec_batch_set_graph": [vp, C.c_int32],
         "ec_batch_set_cells_per_block": [vp, C.c_int32],
-        "ec_batch_autotune": [vp, C.c_int32, C.POINTER(C.c_int32), dp],
+        "ec_batch_autotune": [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp],
+        "ec_batch_set_schedule": [vp, C.c_int32],
         "ec_destroy_batch": [vp],
     }
     for name, args in sigs.items():
@@ -273,6 +279,13 @@ class System:
         _check(self._lib.ec_get_timing(self.h, C.byref(ms), C.byref(n)), self.h, "ec_get_timing")
         return ms.value, n.value
 
+    def get_rebin_timing(self):
+        """(count kernel ms, scatter kernel ms, sweeps) summed over the timed sweeps."""
+        a, b, n = C.c_double(), C.c_double(), C.c_int64()
+        _check(self._lib.ec_get_rebin_timing(self.h, C.byref(a), C.byref(b), C.byref(n)), self.h,
+               "ec_get_rebin_timing")
+        return a.value, b.value, n.value
+
     def sweep_count(self):
         v = C.c_int64()
         _check(self._lib.ec_get_sweep_count(self.h, C.byref(v)), self.h, "ec_get_sweep_count")
@@ -334,12 +347,23 @@ class Batch:
         _check(self._lib.ec_batch_set_cells_per_block(self.h, int(cpb)), self.h,
                "ec_batch_set_cells_per_block", True)
 
+    def set_schedule(self, schedule):
+        """EC_SCHEDULE_* or its name ('phase-launches', 'one-launch', 'ready-queue')."""
+        if isinstance(schedule, str):
+            schedule = SCHEDULE_NAMES.index(schedule)
+        _check(self._lib.ec_batch_set_schedule(self.h, int(schedule)), self.h,
+               "ec_batch_set_schedule", True)
+
     def autotune(self, trial_sweeps=2):
-        cpb = C.c_int32()
-        ms = (C.c_double * 3)()
-        _check(self._lib.ec_batch_autotune(self.h, int(trial_sweeps), C.byref(cpb), ms), self.h,
-               "ec_batch_autotune", True)
-        return cpb.value, {1: ms[0], 2: ms[1], 4: ms[2]}
+        """Time every schedule and cells-per-workgroup choice from a snapshot and
+        keep the fastest: returns (schedule name, cells per workgroup,
+        {(schedule name, cells): ms})"""
+        sched, cpb = C.c_int32(), C.c_int32()
+        ms = (C.c_double * 9)()
+        _check(self._lib.ec_batch_autotune(self.h, int(trial_sweeps), C.byref(sched), C.byref(cpb), ms),
+               self.h, "ec_batch_autotune", True)
+        trials = {f"{SCHEDULE_NAMES[k // 3]}/{(1, 2, 4)[k % 3]}": ms[k] for k in range(9)}
+        return SCHEDULE_NAMES[sched.value], cpb.value, trials
 
     def close(self):
         if getattr(self, "h", None):

@@ -14,13 +14,18 @@ import numpy as np
 # Headline and parity workloads: (name, N, eta, cells per side, ell, sweeps)
 WORKLOADS = {
     # one periodic cell, +x/+y alternating chains
-    "serial_256": dict(n=256, eta=0.70, cells=1, ell=20.0, dir_mode=0, sweeps=200, seed=1),
+    "serial_256": dict(n=256, eta=0.70, cells=1, ell=20.0, dir_mode=0, sweeps=200, seed=1,
+                       label="N=256 eta=0.70, one periodic cell"),
     # 16 x 16 simulation cells, isotropic chains
-    "pec_65k": dict(n=65536, eta=0.70, cells=16, ell=20.0, dir_mode=1, sweeps=1000, seed=1),
+    "pec_65k": dict(n=65536, eta=0.70, cells=16, ell=20.0, dir_mode=1, sweeps=1000, seed=1,
+                    label="N=65536 eta=0.70"),
     # headline: 64 x 64 cells, one million disks
-    "pec_1m": dict(n=1048576, eta=0.72, cells=64, ell=20.0, dir_mode=1, sweeps=500, seed=1),
-    # 256 x 256 cells, 16.7 million disks
-    "pec_16m": dict(n=16777216, eta=0.716, cells=256, ell=30.0, dir_mode=1, sweeps=100, seed=1),
+    "pec_1m": dict(n=1048576, eta=0.72, cells=64, ell=20.0, dir_mode=1, sweeps=500, seed=1,
+                   label="N=1M eta=0.72"),
+    # 256 x 256 cells, 16.7 million disks; FP32 screening with FP64 commits,
+    # pressure and Psi on the device
+    "pec_16m": dict(n=16777216, eta=0.716, cells=256, ell=30.0, dir_mode=1, sweeps=100, seed=1,
+                    precision="fp32-screen", psi6=True, label="N=16.7M eta=0.716"),
 }
 
 

@@ -88,13 +88,17 @@ def test_init_rejects_small_workspace_without_touching_gpu():
 
 
 def test_batch_workspace_is_systems_plus_snapshot():
+    """The batch holds every system's workspace, a snapshot of them (for the
+    autotuner) and the ready queue: 16 bytes per cell of all systems."""
     from tests import inputs
     cfgs = inputs.batch_systems(64, seed=0)
     ps = [P.make_params(c["n"], c["eta"], c["ell"], c["cells"], seed=c["seed"], system=i)
           for i, c in enumerate(cfgs)]
     solo = sum(P.workspace_bytes(p) for p in ps)
+    cells = sum(c["cells"] ** 2 for c in cfgs)
     total = P.batch_workspace_bytes(ps)
-    assert 2 * solo <= total <= 2 * solo + 64 * 2 * 256 + 64 * 1024 + 4096
+    queue = 16 * cells
+    assert 2 * solo + queue <= total <= 2 * solo + queue + 64 * 2 * 256 + 64 * 1024 + 8192
 
 
 def test_batch_rejects_periodic_systems_and_empty_batches():

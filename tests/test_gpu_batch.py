@@ -78,14 +78,17 @@ def test_batch_of_64_equals_solo_runs(P):
     b.close()
 
 
-@pytest.mark.parametrize("cpb", [1, 2, 4])
-def test_batch_graph_and_schedule_keep_trajectories(P, cpb):
+@pytest.mark.parametrize("schedule,cpb", [("ready-queue", 1), ("ready-queue", 2), ("ready-queue", 4),
+                                          ("phase-launches", 1), ("phase-launches", 4),
+                                          ("one-launch", 2)])
+def test_batch_graph_and_schedule_keep_trajectories(P, schedule, cpb):
     cfgs = inputs.batch_systems(64, seed=0)[:12]
     ps = _params(P, cfgs)
     sweeps = 3
-    _say(f"[batch] graph replay, cells per workgroup {cpb}")
+    _say(f"[batch] graph replay, schedule {schedule}, cells per workgroup {cpb}")
     solos = _solo_states(P, ps, sweeps)
     b = P.Batch(ps)
+    b.set_schedule(schedule)
     b.set_cells_per_block(cpb)
     b.set_graph(True)
     b.sweep(1)
@@ -137,9 +140,9 @@ def test_autotune_leaves_the_state_untouched(P):
     solos = _solo_states(P, ps, 3)
     b = P.Batch(ps)
     b.sweep(1)
-    cpb, ms = b.autotune(trial_sweeps=1)
-    _say(f"[batch] autotune chose {cpb} cells per workgroup, trials {ms}")
-    assert cpb in (1, 2, 4)
+    sched, cpb, ms = b.autotune(trial_sweeps=1)
+    _say(f"[batch] autotune chose {sched} with {cpb} cells per workgroup, trials {ms}")
+    assert cpb in (1, 2, 4) and sched in ("phase-launches", "one-launch", "ready-queue")
     assert all(b.systems[i].sweep_count() == 1 for i in range(len(ps)))
     b.set_graph(True)
     b.sweep(2)
@@ -167,4 +170,22 @@ def test_smallest_batch_systems_match_the_oracle(P):
         np.testing.assert_array_equal(y, st.y)
         np.testing.assert_array_equal(b.systems[i].get_digests(sweeps),
                                       np.array(st.digests[-sweeps:], dtype=np.uint64))
+    b.close()
+
+
+def test_batch_fp32_screen_equals_solo_fp64(P):
+    """The FP32-screened batch (the batched workload's form) follows the FP64
+    solo trajectories bit for bit."""
+    cfgs = inputs.batch_systems(64, seed=0)[:16]
+    ps = _params(P, cfgs)
+    sweeps = 2
+    _say("[batch] FP32-screened batch against FP64 solo runs")
+    solos = _solo_states(P, ps, sweeps)
+    for p in ps:
+        p.precision = P.EC_PREC_FP32_SCREEN
+    b = P.Batch(ps)
+    b.set_graph(True)
+    b.sweep(sweeps)
+    b.stream.synchronize()
+    _assert_same(b, solos, sweeps)
     b.close()

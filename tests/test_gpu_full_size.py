@@ -97,8 +97,10 @@ def _replay_and_compare(p, sweep, start_xy, start_tallies, after, targets):
 def test_full_size_cones_of_every_phase_two_sweeps(P, name):
     w = inputs.WORKLOADS[name]
     n, eta, C, ell = w["n"], w["eta"], w["cells"], w["ell"]
-    _say(f"[full-size] {name}: n={n} eta={eta} C={C} ell={ell}: two GPU sweeps")
-    g = P.System(P.make_params(n, eta, ell, C, seed=w["seed"]))
+    _say(f"[full-size] {name}: n={n} eta={eta} C={C} ell={ell}: two GPU sweeps, device overlap check on")
+    # the device's own overlap check runs after each sweep; a pair closer than
+    # sigma would make the next synchronising call raise EC_E_OVERLAP
+    g = P.System(P.make_params(n, eta, ell, C, seed=w["seed"], flags=P.EC_FLAG_CHECK_OVERLAP))
     g.sweep(1)
     s1 = _gpu_state(g)
     g.sweep(1)

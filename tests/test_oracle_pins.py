@@ -1004,3 +1004,72 @@ def test_dependency_cone_replays_later_phases():
                 assert st.acc_delta[c] == ref.acc_delta[c]
                 np.testing.assert_array_equal(st.acc_cnt[c], ref.acc_cnt[c])
             assert len(dig) == len(cells)
+
+
+# --------------------------------------------------------------------------
+# Striped decomposition with rejection (Sec. 3.4, Fig. 3 "stripes"; Sec. 4)
+# --------------------------------------------------------------------------
+def _image(d, L):
+    return d - L * np.round(d / L)
+
+
+@pytest.mark.parametrize("n,eta,stripes,ell,kw", [
+    (4096, 0.70, 8, 0.3, {}),
+    (1024, 0.30, 4, 3.0, {}),
+    (64, 0.10, 4, 30.0, {}),   # flights beyond the nearest-image range: pseudo events
+    (1024, 0.60, 4, 0.5, dict(chains_per_cell=50, start_mode=O.START_DISTINCT)),
+])
+def test_stripes_invariants(n, eta, stripes, ell, kw):
+    """Chains run along the stripes: on even sweeps every y keeps its bits and
+    the x displacements of all disks add up to ell times a sum of signs, one
+    +-1 per accepted chain (odd sweeps: the same with x and y exchanged), so
+    the total over ell is an integer of the parity of the accepted count;
+    rejected chains leave no trace; no two disks overlap."""
+    p = O.params(n, eta, ell, stripes, dir_mode=O.DIR_XY, boundary=O.BOUNDARY_STRIPES, seed=3, **kw)
+    L = O.box_length(n, 1.0, eta)
+    st = O.State(p)
+    for sweep in range(4):
+        x0, y0 = st.x.copy(), st.y.copy()
+        cnt0 = st.acc_cnt.sum(axis=0).copy()
+        st.run(1)
+        cnt = st.acc_cnt.sum(axis=0) - cnt0
+        along0, along1, across0, across1 = ((x0, st.x, y0, st.y) if sweep % 2 == 0
+                                            else (y0, st.y, x0, st.x))
+        np.testing.assert_array_equal(across1, across0)
+        accepted = int(cnt[O.CNT_CHAINS]) - int(cnt[O.CNT_FROZEN])
+        assert cnt[O.CNT_WALLS] == 0
+        assert int(cnt[O.CNT_CHAINS]) == (n if not kw else 50 * stripes)
+        if 4 * ell < L / 2:  # a disk's net move stays below L/2, so nearest images add up
+            m = _image(along1 - along0, L).sum() / ell
+            assert abs(m - round(m)) < 1e-9 * max(1.0, accepted)
+            assert abs(round(m)) <= accepted and (round(m) - accepted) % 2 == 0
+        d, _, _ = O.min_pair_distance(st.x, st.y, L, r_cut=1.0 - 1e-12)
+        assert d == math.inf
+    if eta == 0.10:
+        assert st.acc_cnt[:, O.CNT_PSEUDO].sum() > 0
+
+
+def test_stripes_two_disks_periodic_exact():
+    """Two disks in a periodic L x L box swept by the striped decomposition
+    (4 stripes, rejection at the stripe boundaries, starts with replacement):
+    the stationary law makes the separation uniform on the torus minus the
+    disk of radius sigma, so P(|r| < R) = pi (R^2 - sigma^2) / (L^2 - pi sigma^2)
+    for R <= L/2."""
+    L = 8.8
+    eta = 2 * math.pi / (4 * L * L)
+    p = O.params(2, eta, 1.5, 4, dir_mode=O.DIR_XY, boundary=O.BOUNDARY_STRIPES, seed=8)
+    st = O.State(p, np.array([1.0, 5.0]), np.array([1.0, 3.0]))
+    sweeps = 40000
+    rs = np.empty(sweeps)
+    for t in range(sweeps // 1000):
+        for k in range(1000):
+            st.run(1)
+            rs[t * 1000 + k] = math.hypot(_image(st.x[1] - st.x[0], L), _image(st.y[1] - st.y[0], L))
+    assert rs.min() >= 1.0 - 1e-12
+    edges = np.array([1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0, 4.4])
+    exact = np.diff(math.pi * (edges ** 2 - 1.0) / (L * L - math.pi))
+    B = 40
+    m = sweeps // B
+    f = np.array([np.histogram(rs[b * m:(b + 1) * m], bins=edges)[0] / m for b in range(B)])
+    z = (f.mean(0) - exact) / (f.std(0, ddof=1) / math.sqrt(B))
+    assert np.abs(z).max() < 4.5, z
