@@ -380,6 +380,33 @@ const char* ec_batch_last_error(ec_batch b);
 /* Destroy the batch and its system handles (not the workspace).  Synchronises. */
 ec_status ec_destroy_batch(ec_batch b);
 
+/* ---- Sweeps without allocation -------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The same
+ * sweeps as ec_init_system + ec_sweep, with the positions in caller device
+ * buffers and every other piece of state (cell lists, chain draws, tallies,
+ * counters, the device record) in one static device buffer of the library,
+ * 10 MiB per GPU, held until the process ends.
+ *
+ * x[n], y[n]: device arrays, disk-id order, coordinates in [0, L) of a
+ * non-overlapping configuration (not checked; ec_set_positions's checks are
+ * the caller's to make), advanced in place by sweeps first_sweep ..
+ * first_sweep + n_sweeps - 1 of the system p describes (its seed keys the
+ * random streams as in ec_init_system, whose first sweep is number 0).
+ * digests (may be NULL): device uint64[n_sweeps], the per-sweep event digests
+ * (n_sweeps <= 1024 then).  err (may be NULL): device int32, the device error
+ * bits of ec_last_error's message (0 = none) after the last sweep.  Every
+ * operation is enqueued on hip_stream (NULL = null stream); nothing is
+ * allocated, copied to or from the host, or synchronised.
+ *
+ * Errors: EC_E_INVALID / EC_E_UNSUPPORTED as ec_init_system; EC_E_NOMEM if
+ * the system exceeds the static buffer (N > 262144 disks, or more cells or
+ * chains than 10 MiB holds); EC_E_HIP for a failed launch.  Every call on a
+ * GPU uses that GPU's one buffer and clears it first: calls that overlap on
+ * one GPU (other streams, other host threads) race and corrupt each other. */
+ec_status ec_sweep_static(const ec_params* p, double* x, double* y, int64_t first_sweep,
+                          int64_t n_sweeps, uint64_t* digests, int32_t* err, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libec_hip.so")
 SOURCES = [os.path.join(CSRC, "ec_kernels.hip"), os.path.join(CSRC, "ec_observe.hip"),
-           os.path.join(CSRC, "ec_api.cpp")]
+           os.path.join(CSRC, "ec_static.hip"), os.path.join(CSRC, "ec_api.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

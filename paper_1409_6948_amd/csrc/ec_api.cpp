@@ -1266,6 +1266,44 @@ ec_status ec_batch_autotune(ec_batch b, int32_t trial_sweeps, int32_t* schedule_
 
 const char* ec_batch_last_error(ec_batch b) { return b ? b->last_error.c_str() : ""; }
 
+// ---------------------------------------------------------------------------
+// Allocation-free sweeps: the state of ec_sweep lives in the static buffer
+// ---------------------------------------------------------------------------
+ec_status ec_sweep_static(const ec_params* p, double* x, double* y, int64_t first_sweep,
+                          int64_t n_sweeps, uint64_t* digests, int32_t* err, void* stream) {
+  if (!x || !y || first_sweep < 0 || n_sweeps < 0) return EC_E_INVALID;
+  if (digests && n_sweeps > ec::kDigestRing) return EC_E_INVALID;
+  Derived dv;
+  std::string why;
+  ec_status st = validate(p, &dv, &why);
+  if (st != EC_OK) return st;
+  if (p->n_disks > ec::kStaticMaxDisks) return EC_E_NOMEM;
+  const Layout lay = make_layout(p->n_disks, p->cells_per_side, p->chains_per_cell, true);
+  if (lay.total > ec::kStaticScratchBytes) return EC_E_NOMEM;
+  void* base = nullptr;
+  if (ec::static_scratch(&base) != hipSuccess) return EC_E_HIP;
+  if (prepare_kernels() != hipSuccess) return EC_E_HIP;
+  unsigned char* b = (unsigned char*)base;
+  ec::Dev d;
+  fill_record(&d, p, dv, b, lay);
+  d.x = x;  // the caller's positions; no observables in this form
+  d.y = y;
+  d.psi = nullptr;
+  d.psi_part = nullptr;
+  d.psi_red = nullptr;
+  d.psi_nb = nullptr;
+  d.psi_err = nullptr;
+  d.gr_counts = nullptr;
+  ec::Dev* dd = (ec::Dev*)(b + lay.dev);
+  const ec::LaunchShape sh = shape_of(d, *p);
+  const hipStream_t hs = (hipStream_t)stream;
+  hipError_t e = ec::launch_static_setup(d, dd, b, lay.total, first_sweep, hs);
+  for (int64_t i = 0; i < n_sweeps && e == hipSuccess; ++i) e = ec::launch_sweep(dd, sh, hs);
+  if (e == hipSuccess)
+    e = ec::launch_static_copy_out(dd, first_sweep, digests ? n_sweeps : 0,
+                                   (unsigned long long*)digests, err, hs);
+  return e == hipSuccess ? EC_OK : EC_E_HIP;
+}
 
 ec_status ec_destroy_batch(ec_batch b) {
   if (!b) return EC_E_INVALID;

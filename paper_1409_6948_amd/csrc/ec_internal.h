@@ -212,6 +212,21 @@ hipError_t launch_psi6(const Dev* ds, const LaunchShape& sh, double r_cut, hipSt
 hipError_t launch_psi6_delaunay(const Dev* ds, const LaunchShape& sh, double r_search, hipStream_t st);
 hipError_t launch_gr(const Dev* ds, const LaunchShape& sh, double r_max, double delta, int n_bins,
                      hipStream_t st);
+// Allocation-free sweeps (ec_sweep_static): bytes of the library's static
+// device buffer (one per GPU) and the largest system it holds.
+constexpr size_t kStaticScratchBytes = size_t(10) << 20;
+constexpr int64_t kStaticMaxDisks = int64_t(1) << 18;
+// Address of this GPU's static buffer (looked up once per device).
+hipError_t static_scratch(void** ptr);
+// Clear [base, base + bytes) with a kernel, then store rec at dst and the
+// number of the first sweep in rec.sweep_ctr.
+hipError_t launch_static_setup(const Dev& rec, Dev* dst, unsigned char* base, size_t bytes,
+                               int64_t first_sweep, hipStream_t st);
+// Digests of sweeps first .. first + n - 1 and the device error word into
+// caller device buffers (either may be null).
+hipError_t launch_static_copy_out(const Dev* ds, int64_t first, int64_t n,
+                                  unsigned long long* digests, int32_t* err, hipStream_t st);
+
 // Debug check after a sweep: every pair of disks in neighbouring cells of the
 // sweep's grid (all pairs for one periodic cell) closer than sigma (1 - 1e-12)
 // is counted in ovl and sets ERR_OVERLAP.  Systems without check_overlap skip it.

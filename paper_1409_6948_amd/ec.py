@@ -36,7 +36,8 @@ EXPORTED = ("ec_workspace_bytes", "ec_init_system", "ec_sweep", "ec_measure_pres
             "ec_batch_system", "ec_batch_set_graph", "ec_batch_set_cells_per_block",
             "ec_batch_autotune", "ec_batch_set_schedule", "ec_batch_last_error", "ec_destroy_batch", "ec_measure_psi6",
             "ec_measure_psi6_delaunay", "ec_psi_autocorrelation",
-            "ec_gr_accumulate", "ec_gr_counts", "ec_gr_reset", "ec_gr_normalize")
+            "ec_gr_accumulate", "ec_gr_counts", "ec_gr_reset", "ec_gr_normalize",
+            "ec_sweep_static")
 
 
 class ECError(RuntimeError):
@@ -106,6 +107,7 @@ def load_library():
         "ec_batch_autotune": [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp],
         "ec_batch_set_schedule": [vp, C.c_int32],
         "ec_destroy_batch": [vp],
+        "ec_sweep_static": [P, vp, vp, C.c_int64, C.c_int64, vp, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -377,6 +379,23 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def sweep_static(p, x, y, first_sweep, n_sweeps, digests=None, err=None, stream=None):
+    """ec_sweep_static: sweeps of device-resident positions (torch float64
+    tensors on the GPU, advanced in place) with the library's static buffer;
+    digests (torch int64[n_sweeps]) and err (torch int32[1]) are optional
+    device outputs.  Enqueued on `stream` (default: torch's current stream)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    for t in (x, y):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != p.n_disks:
+            raise ValueError("x and y must be contiguous float64 CUDA tensors of n_disks elements")
+    _check(load_library().ec_sweep_static(
+        C.byref(p), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), int(first_sweep),
+        int(n_sweeps), C.c_void_p(digests.data_ptr()) if digests is not None else None,
+        C.c_void_p(err.data_ptr()) if err is not None else None, C.c_void_p(st.cuda_stream)),
+        what="ec_sweep_static")
 
 
 def psi_autocorrelation(psi, max_lag):
