@@ -206,6 +206,8 @@ def main():
     prec = P.EC_PREC_FP64 if precision == "fp64" else P.EC_PREC_FP32_SCREEN
     flags = SCHEDULE_FLAGS[args.schedule](P)
     kernel = "k_phase" if args.schedule == "phase-launches" else "k_sweep_cells"
+    if w["cells"] == 1:
+        kernel = "k_periodic"  # one periodic cell: N serial chains in one wavefront
     p = P.make_params(w["n"], w["eta"], w["ell"], w["cells"], dir_mode=w["dir_mode"],
                       seed=w["seed"], cells_per_block=args.cells_per_block, precision=prec,
                       flags=flags)
@@ -293,9 +295,11 @@ def main():
         "dtype": "f64" if precision == "fp64" else "f32-screen+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_disks": w["n"], "eta": w["eta"],
-                   "cells_per_side": w["cells"], "ell": w["ell"], "directions": "isotropic",
+                   "cells_per_side": w["cells"], "ell": w["ell"],
+                   "directions": "isotropic" if w["dir_mode"] == 1 else "+x/+y alternating",
                    "precision": precision,
-                   "schedule": "phase-launches" if kernel == "k_phase" else "one-launch",
+                   "schedule": {"k_phase": "phase-launches", "k_periodic": "one periodic cell"}.get(
+                       kernel, "one-launch"),
                    "start": "lattice",
                    "sweeps_before_timing": args.warmup},
         "sweeps_per_s": sweeps_s,

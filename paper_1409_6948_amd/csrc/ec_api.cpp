@@ -162,8 +162,17 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
     }
     double w = L / (double)C;
     if (!(w > p->sigma)) { *why = "cell side must exceed sigma"; return EC_E_INVALID; }
-    int32_t nb = (int32_t)std::floor(w / p->sigma);
-    if (nb < 3) { *why = "cell side below 3 sigma is not supported"; return EC_E_UNSUPPORTED; }
+    if (std::floor(w / p->sigma) < 3) {
+      *why = "cell side below 3 sigma is not supported"; return EC_E_UNSUPPORTED;
+    }
+    // nb x nb bins of side b = w / nb < 0.7 sigma (< sigma / sqrt 2, so a bin
+    // holds at most one centre) and, as w >= 3 sigma, b > 0.56 sigma (two
+    // rings of bins outside the cell hold the sigma-wide frozen band)
+    const int32_t nb = (int32_t)std::floor(w / (0.7 * p->sigma)) + 1;
+    const double b = w / (double)nb;
+    if (!(b < 0.7 * p->sigma) || !(2.0 * b > p->sigma)) {
+      *why = "internal: bin side out of range"; return EC_E_UNSUPPORTED;
+    }
     if (p->n_disks > (int64_t(1) << 29) - 4) {
       *why = "walled cells support at most 2^29 - 4 disks"; return EC_E_UNSUPPORTED;
     }
@@ -171,7 +180,10 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
     out->nb = nb;
     out->cap_own = own_capacity(w, p->sigma);
     out->lds_per_cell =
-        ec::cell_lds_layout(nb + 2, out->cap_own, (p->flags & EC_FLAG_REJECT) != 0).bytes;
+        ec::cell_lds_layout(nb + 4, out->cap_own, (p->flags & EC_FLAG_REJECT) != 0).bytes;
+    if (4 * out->cap_own > 16 * (nb + 4) * (nb + 4)) {  // the staging ids live in the slots
+      *why = "internal: staging buffer"; return EC_E_UNSUPPORTED;
+    }
     // Default: four cells (four waves) per workgroup when their LDS fits one CU.
     // The waves of one workgroup go to the four SIMDs of one CU; one-wave
     // workgroups leave the SIMD choice to the dispatcher, which has been
@@ -304,7 +316,8 @@ ec::LaunchShape shape_of(const ec::Dev& d, const ec_params& p) {
 }
 
 // Error bounds of the FP32 screen.  With u = 2^-24, coordinates of staged
-// disks bounded by X = w + 2 sigma and window offsets by R = 6b, the FP32
+// disks bounded by X = w + 2 sigma and window offsets by R = 9b (an 8 x 8-bin
+// window reaches at most 6 bins along each axis from the moving disk), the FP32
 // offsets are within u (2X + R) of the exact ones, so a = r.d and c = r x d
 // are within Ea = u (4X + 8R) (also covering the FP64 values), sigma^2 - c^2
 // within Ed = 2 (sigma + Ea) Ea + 4 u sigma^2, and where the FP32
@@ -313,7 +326,7 @@ ec::LaunchShape shape_of(const ec::Dev& d, const ec_params& p) {
 // relative margin (times sigma) is added to the distance bound.
 void screen_bounds(ec::Dev* d) {
   const double u = std::ldexp(1.0, -24);
-  const double sg = d->sigma, X = d->w + 2.0 * sg, R = 6.0 * d->b;
+  const double sg = d->sigma, X = d->w + 2.0 * sg, R = 9.0 * d->b;
   const double ea = 2.0 * u * (4.0 * X + 8.0 * R);
   const double ed = 2.0 * (2.0 * (sg + ea) * ea + 4.0 * u * sg * sg);
   const double dg = sg * sg / 64.0;
@@ -376,7 +389,7 @@ void fill_record(ec::Dev* out, const ec_params* p, const Derived& dv, unsigned c
   d.cap = 0.5 * dv.L - p->sigma;
   d.C = p->cells_per_side;
   d.nb = dv.nb;
-  d.gridb = dv.nb + 2;
+  d.gridb = dv.nb + 4;  // own bins 2..nb+1, two rings of frozen-band bins around them
   d.b = dv.nb > 0 ? dv.w / (double)dv.nb : 0.0;
   d.inv_b = dv.nb > 0 ? 1.0 / d.b : 0.0;
   d.margin = p->screen_margin > 0.0 ? p->screen_margin : 1e-5;  // relative to sigma

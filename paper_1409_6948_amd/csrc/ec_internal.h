@@ -117,25 +117,25 @@ struct Dev {
   uint32_t system;
 };
 
-// LDS layout of one simulation cell in the walled-cell kernel: per slot an
-// FP64 position and a 64-bit word (disk id | frozen bit, local own index);
-// then the own-disk tables and one sink slot per lane (a target for the
-// lanes that do not store when one lane writes a position).
+// LDS layout of one simulation cell in the walled-cell kernel: a grid of
+// gridb x gridb square bins of side b < sigma/sqrt(2), one slot each (FP64
+// position, 32-bit meta word: own index, or frozen id | top bit); the cell's
+// id-ordered list and the slot of each own disk; one sink slot per lane (a
+// target for the lanes that do not store when one or two lanes write).
 struct CellLds {
-  int32_t off_pos, off_meta, off_mask, off_own_gid, off_own_loc, off_tmp, off_sink, off_undo, bytes;
+  int32_t off_pos, off_meta, off_own_gid, off_own_loc, off_sink, off_undo, bytes;
 };
 
 // reject: an undo log of kUndoCap entries (slots and old position, 32 B each).
 __host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own, bool reject) {
   CellLds l;
-  int slots = gridb * gridb * 4;
+  int slots = gridb * gridb;
   int o = 0;
   l.off_pos = o;      o += 16 * slots;
-  l.off_meta = o;     o += 8 * slots;
-  l.off_mask = o;     o += 4 * gridb * gridb;
+  l.off_meta = o;     o += 4 * slots;
+  o = (o + 15) & ~15;
   l.off_own_gid = o;  o += 4 * cap_own;
   l.off_own_loc = o;  o += 4 * cap_own;
-  l.off_tmp = o;      o += 4 * cap_own;
   o = (o + 15) & ~15;
   l.off_sink = o;     o += 16 * 64;
   l.off_undo = o;     o += reject ? 32 * kUndoCap : 0;

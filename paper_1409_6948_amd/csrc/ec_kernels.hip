@@ -7,16 +7,17 @@
 //
 // Mapping to CDNA4: one wavefront (64 lanes) per active simulation cell.  A
 // cell's own disks and its frozen neighbours (centres within sigma outside
-// the cell) are staged in LDS in a grid of square bins of side b in
-// [sigma, 4/3 sigma); such a bin holds at most four non-overlapping centres,
-// so four slots per bin suffice.  One event search reads a 4 x 4 window of
-// bins around the moving disk, one slot per lane, computes the contact
-// distance of every slot in FP64, and takes a wave-wide minimum of the key
-// (distance, disk id).  A geometric guard proves that no disk outside the
-// window can be hit first; when it cannot (long free flights), the search is
-// repeated over all slots of the cell.  The event found is therefore exactly
-// the minimum over all candidate disks, in the same arithmetic as a plain
-// serial search.
+// the cell) are staged in LDS in a grid of square bins of side b <
+// sigma/sqrt(2); such a bin holds at most one centre of a configuration
+// without overlaps, so one slot per bin suffices and a cell takes about 20 KB
+// (eight cells, two wavefronts per SIMD, per CU).  One event search reads an
+// 8 x 8 window of bins around the moving disk, one slot per lane, computes
+// the contact distance of every slot in FP64, and takes a wave-wide minimum
+// of the key (distance, disk id).  A geometric guard proves that no disk
+// outside the window can be hit first; when it cannot (long free flights),
+// the search is repeated over all slots of the cell.  The event found is
+// therefore exactly the minimum over all candidate disks, in the same
+// arithmetic as a plain serial search.
 //
 // Arithmetic contract (shared in writing with the CPU reference, no code
 // shared): FP64 with no contraction (-ffp-contract=off) and explicit fma();
@@ -277,14 +278,18 @@ __device__ __forceinline__ unsigned wave_xor_all(unsigned v) {
 
 // Digest terms of the first `count` event records held one per lane (lane k:
 // record of event first + k, in three 32-bit registers: the step's bits and
-// kind << 29 | id), XOR-ed over the wave.
+// kind << 29 | id, where a lift (kind 1) names its disk by the index into the
+// cell's id-ordered list own_gid), XOR-ed over the wave.
 __device__ __forceinline__ uint64_t digest_batch(uint32_t rec_lo, uint32_t rec_hi, uint32_t rec_tag,
-                                                 int lane, int count, uint64_t first) {
+                                                 int lane, int count, uint64_t first,
+                                                 const int32_t* own_gid) {
   uint64_t t = 0;
   if (lane < count) {
     const uint64_t sb = ((uint64_t)rec_hi << 32) | rec_lo;
-    t = digest_term((int)(rec_tag >> 29), rec_tag & 0x1FFFFFFFu,
-                    __longlong_as_double((long long)sb), first + (uint64_t)lane);
+    const int kind = (int)(rec_tag >> 29);
+    uint32_t id = rec_tag & 0x1FFFFFFFu;
+    if (kind == 1) id = (uint32_t)own_gid[id];
+    t = digest_term(kind, id, __longlong_as_double((long long)sb), first + (uint64_t)lane);
   }
   const uint32_t lo = (uint32_t)uniform_i32((int)wave_xor_all((uint32_t)t));
   const uint32_t hi = (uint32_t)uniform_i32((int)wave_xor_all((uint32_t)(t >> 32)));
@@ -589,7 +594,37 @@ __global__ void k_shuffle(const Dev* __restrict__ ds) {
 // ---------------------------------------------------------------------------
 // Walled simulation cells: one wavefront per active cell of colour perm[q]
 // ---------------------------------------------------------------------------
+// Meta word of a slot: an own disk's index into the cell's id-ordered list,
+// or a frozen disk's id with the top bit set; all ones while staging finds
+// the slot empty.
 constexpr uint32_t kFrozenBit = 0x80000000u;
+constexpr uint32_t kEmptySlot = 0xFFFFFFFFu;
+
+// Lane of the smallest key (s, id) among the window's candidates, given the
+// wave minimum mn of their high words hi (as argmin_lane); the ids are taken
+// only on the rare path of equal high words: a frozen disk's from its meta
+// word, an own disk's from the cell's id list.
+__device__ __forceinline__ int argmin_lane_slots(double s, uint32_t m, const int32_t* own_gid,
+                                                 unsigned hi, unsigned mn) {
+  const uint64_t sb = (uint64_t)__double_as_longlong(s);
+  uint64_t mask = __builtin_amdgcn_ballot_w64(hi == mn);  // not empty: some lane holds mn
+  int wl = __builtin_ctzll(mask);
+  if (__builtin_expect(mask != (1ull << wl), 0)) {  // equal high words: resolve on the full key
+    uint32_t id = 0;
+    if (hi == mn) id = (m & kFrozenBit) ? (m & ~kFrozenBit) : (uint32_t)own_gid[m];
+    mask &= mask - 1;
+    uint64_t bs = readlane_u64(sb, wl);
+    uint32_t bi = (uint32_t)readlane_i32((int)id, wl);
+    while (mask) {
+      const int l = __ffsll((unsigned long long)mask) - 1;
+      mask &= mask - 1;
+      const uint64_t ls = readlane_u64(sb, l);
+      const uint32_t li = (uint32_t)readlane_i32((int)id, l);
+      if (ls < bs || (ls == bs && li < bi)) { bs = ls; bi = li; wl = l; }
+    }
+  }
+  return wl;
+}
 
 __device__ __forceinline__ int32_t load_err(const Dev& d) {
   return __hip_atomic_load(d.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -614,18 +649,20 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
   const double ox = (double)cx * d.w, oy = (double)cy * d.w;
   const double L = d.L, half_L = d.half_L, w = d.w, sigma = d.sigma, sig2 = d.sig2;
   const int gridb = d.gridb, nb = d.nb;
-  const int nslots = gridb * gridb * 4;
+  const int nslots = gridb * gridb;  // one slot per bin
 
   const CellLds lay = cell_lds_layout(gridb, d.cap_own, REJ == 1);
   double2* pos = (double2*)(base + lay.off_pos);
-  uint64_t* meta = (uint64_t*)(base + lay.off_meta);
-  int32_t* mask = (int32_t*)(base + lay.off_mask);
+  uint32_t* meta = (uint32_t*)(base + lay.off_meta);
   int32_t* own_gid = (int32_t*)(base + lay.off_own_gid);
   int32_t* own_loc = (int32_t*)(base + lay.off_own_loc);
-  int32_t* tmp = (int32_t*)(base + lay.off_tmp);
-  // per-lane sink slots: lanes other than 0 write here when lane 0 stores the
-  // moved disk, so the store needs no change of the execution mask
+  // the id staging buffer of the rank sort lies in the position slots, which
+  // are filled only after the sort
+  int32_t* tmp = (int32_t*)(base + lay.off_pos);
+  // per-lane sink slots: lanes that have nothing to store write here, so a
+  // store by one or two lanes needs no change of the execution mask
   double2* const sink = (double2*)(base + lay.off_sink) + lane;
+  uint32_t* const sink32 = (uint32_t*)sink;
   // REJ 1 only: per logged lift the old position, then (slot before, slot after)
   double2* undo_pos = (double2*)(base + lay.off_undo);
   int2* undo_slot = (int2*)(undo_pos + kUndoCap);
@@ -645,28 +682,34 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     for (int j = 0; j < n_own; ++j) r += (tmp[j] < v) ? 1 : 0;
     own_gid[r] = v;
   }
+  wave_sync();
   const double2 nan2 = make_double2(__builtin_nan(""), __builtin_nan(""));
-  for (int s = lane; s < nslots; s += 64) pos[s] = nan2;
-  for (int bi = lane; bi < gridb * gridb; bi += 64) mask[bi] = 0;
+  for (int s = lane; s < nslots; s += 64) {
+    pos[s] = nan2;
+    meta[s] = kEmptySlot;
+  }
   wave_sync();
 
-  // own disks into bins 1..nb (mask[] counts during staging)
+  // own disks into bins 2..nb+1: a bin's diagonal is below sigma, so it holds
+  // at most one centre of a configuration without overlaps (a second one is
+  // reported as a capacity error)
   for (int k = lane; k < n_own; k += 64) {
     int g = own_gid[k];
     double vx = local_coord(d.x[g], dr.sx, ox, L, half_L);
     double vy = local_coord(d.y[g], dr.sy, oy, L, half_L);
-    int bx = (int)floor(vx * d.inv_b) + 1, by = (int)floor(vy * d.inv_b) + 1;
-    bx = bx < 1 ? 1 : (bx > nb ? nb : bx);
-    by = by < 1 ? 1 : (by > nb ? nb : by);
-    int bin = by * gridb + bx;
-    int slot = atomicAdd(&mask[bin], 1);
-    if (slot >= 4) { atomicOr(d.err, ERR_BIN_CAP); continue; }
-    int s = bin * 4 + slot;
+    int bx = (int)floor(vx * d.inv_b) + 2, by = (int)floor(vy * d.inv_b) + 2;
+    bx = bx < 2 ? 2 : (bx > nb + 1 ? nb + 1 : bx);
+    by = by < 2 ? 2 : (by > nb + 1 ? nb + 1 : by);
+    const int s = by * gridb + bx;
+    if (atomicCAS(&meta[s], kEmptySlot, (uint32_t)k) != kEmptySlot) {
+      atomicOr(d.err, ERR_BIN_CAP);
+      continue;
+    }
     pos[s] = make_double2(vx, vy);
-    meta[s] = ((uint64_t)(uint32_t)k << 32) | (uint32_t)g;
     own_loc[k] = s;
   }
-  // frozen disks: centres of the 8 neighbouring cells within sigma of this cell
+  // frozen disks: centres of the 8 neighbouring cells within sigma of this
+  // cell, in the two outer rings of bins
   for (int nbh = 0; nbh < 9; ++nbh) {
     if (nbh == 4) continue;
     int ncx = (cx + (nbh % 3) - 1 + d.C) % d.C;
@@ -682,22 +725,17 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       double vx = local_coord(d.x[g], dr.sx, ox, L, half_L);
       double vy = local_coord(d.y[g], dr.sy, oy, L, half_L);
       if (vx >= -sigma && vx <= w + sigma && vy >= -sigma && vy <= w + sigma) {
-        int bx = (int)floor(vx * d.inv_b) + 1, by = (int)floor(vy * d.inv_b) + 1;
-        bx = bx < 0 ? 0 : (bx > nb + 1 ? nb + 1 : bx);
-        by = by < 0 ? 0 : (by > nb + 1 ? nb + 1 : by);
-        int bin = by * gridb + bx;
-        int slot = atomicAdd(&mask[bin], 1);
-        if (slot >= 4) { atomicOr(d.err, ERR_BIN_CAP); continue; }
-        int s = bin * 4 + slot;
+        int bx = (int)floor(vx * d.inv_b) + 2, by = (int)floor(vy * d.inv_b) + 2;
+        bx = bx < 0 ? 0 : (bx > nb + 3 ? nb + 3 : bx);
+        by = by < 0 ? 0 : (by > nb + 3 ? nb + 3 : by);
+        const int s = by * gridb + bx;
+        if (atomicCAS(&meta[s], kEmptySlot, (uint32_t)g | kFrozenBit) != kEmptySlot) {
+          atomicOr(d.err, ERR_BIN_CAP);
+          continue;
+        }
         pos[s] = make_double2(vx, vy);
-        meta[s] = (0xFFFFFFFFull << 32) | ((uint32_t)g | kFrozenBit);
       }
     }
-  }
-  wave_sync();
-  for (int bi = lane; bi < gridb * gridb; bi += 64) {
-    int c = mask[bi];
-    mask[bi] = (c >= 4) ? 0xF : ((1 << c) - 1);
   }
   wave_sync();
   if (load_err(d) != 0) return;  // a capacity check failed somewhere: do not run chains
@@ -711,21 +749,23 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
   int n_ring = 0;            // event records held in the lanes (lane k: record k)
   uint64_t ring_first = 0;    // digest index of record 0
   uint32_t rec_lo = 0, rec_hi = 0, rec_tag = 0;
-  // lane = ks + 4 lx + 16 ly: the four slots of a bin in neighbouring lanes,
-  // so the 16 lanes of one window row read 256 contiguous bytes (no LDS bank
-  // conflicts between rows)
-  const int lx = lane & 3, ly = (lane >> 2) & 3, ks = lane >> 4;
-  const int loff = ((ly * gridb) + lx) * 4 + ks;  // this lane's slot inside a window
+  // lane = lx + 8 ly: one bin of an 8 x 8 window per lane, a window row in 8
+  // neighbouring lanes
+  const int lx = lane & 7, ly = lane >> 3;
+  const int loff = ly * gridb + lx;  // this lane's slot inside a window
   const double inv_b = d.inv_b;
-  // A window of 4 x 4 bins extends at least 2b ahead of the moving disk's bin
-  // and at least b behind it along each axis (clamped windows only add room,
-  // since nothing is staged beyond the outer bins).  With b >= sigma + eps, a
-  // move of length t keeps its sigma-neighbourhood inside the window whenever
-  // t * max(|dx|, |dy|) <= 2b - sigma - eps: then no disk outside the window
-  // can be hit first, and the event found in the window is exact.
+  // A window of 8 x 8 bins reaches 2 bins behind the moving disk's bin and 5
+  // ahead of it along each axis (clamped windows only add room, since nothing
+  // is staged beyond the outer bins).  With sigma/2 < b < sigma/sqrt(2), the
+  // 2b behind cover sigma, and a move of length t keeps its
+  // sigma-neighbourhood inside the window whenever t * max(|dx|, |dy|) <=
+  // 5b - sigma - eps: then no disk outside the window can be hit first, and
+  // the event found in the window is exact.
   const double eps = 1e-9 * sigma;
-  const double reach = 2.0 * d.b - sigma - eps;
-  const bool use_window = d.search == 0 && d.b >= sigma + eps;
+  const double reach = 5.0 * d.b - sigma - eps;
+  // a plain lift keeps the moved centre in [wlo, whi] on both axes (see there)
+  const double wlo = eps, whi = w - eps;
+  const bool use_window = d.search == 0;
   const uint64_t wall_x_id = (uint64_t)d.n, wall_y_id = (uint64_t)d.n + 1, end_id = (uint64_t)d.n + 3;
   int aborted = 0;
   int stop = 0;  // nonzero once a poll sees the device error word set
@@ -761,21 +801,20 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       xneg = uniform_i32(dx < 0.0 ? 1 : 0);                                         \
       yneg = uniform_i32(dy < 0.0 ? 1 : 0);                                         \
     } while (0)
-    // origin bin of the 4 x 4-bin window around bin (bx, by): one bin behind
-    // the disk and two ahead of it along each axis, clamped to the grid
+    // origin bin of the 8 x 8-bin window around bin (bx, by): two bins behind
+    // the disk and five ahead of it along each axis, clamped to the grid
 #define EC_WINDOW(bx, by, xn, yn)                                                   \
     do {                                                                            \
-      wx0 = (bx) - 1 - (xn);                                                        \
-      wy0 = (by) - 1 - (yn);                                                        \
-      wx0 = max(min(wx0, gridb - 4), 0);                                            \
-      wy0 = max(min(wy0, gridb - 4), 0);                                            \
-      wbase = (wy0 * gridb + wx0) * 4;                                              \
+      wx0 = (bx) - 2 - 3 * (xn);                                                    \
+      wy0 = (by) - 2 - 3 * (yn);                                                    \
+      wx0 = max(min(wx0, gridb - 8), 0);                                            \
+      wy0 = max(min(wy0, gridb - 8), 0);                                            \
+      wbase = wy0 * gridb + wx0;                                                    \
     } while (0)
     EC_SET_DIRECTION();
     int a_loc = uniform_i32(own_loc[j]);
     int a_lidx = j;
-    uint32_t a_gid = (uint32_t)uniform_i32(own_gid[j]);
-    int abx = (a_loc >> 2) % gridb, aby = (a_loc >> 2) / gridb;
+    int abx = a_loc % gridb, aby = a_loc / gridb;
     const double2 ap = pos[a_loc];
     double ax = ap.x, ay = ap.y;
     double rem = d.ell;
@@ -792,14 +831,14 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     EC_WINDOW(abx, aby, xneg, yneg);
     int widx = wbase + loff;  // this lane's slot in the window
     double2 p = pos[widx];
-    uint64_t m = meta[widx];
+    uint32_t m = meta[widx];
     int ended = 0;  // the chain length is used up
 
     while (ended == 0 && stop == 0 && n_polls < kMaxPolls) {
       // the event found, and the decision (also read by the general path)
       double tx, ty, best_s, wpx, wpy, e, step, nax, nay;
-      uint32_t wgid;
-      int w_lidx, w_bx, w_by, w_slot, packed;
+      uint32_t wm;  // meta word of the nearest disk: own index, or id | frozen bit
+      int w_bx, w_by, w_slot, packed;
       int found;  // a disk can be hit (wave-uniform)
       // Plain lifts run in this inner loop, where the direction and its
       // derived constants do not change: the general path, which can change
@@ -851,12 +890,15 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       // The plain-lift test (the conditions are listed where its result is
       // read) made by every lane on its own candidate while the wave minimum
       // forms, so that it fills the DPP hazard slots; only the winning lane's
-      // result is used, computed with the winner's own values.
-      int plain_l;
+      // result is used, computed with the winner's own values.  The lane also
+      // forms the slot of the moved centre's bin.
+      int plain_l, nslot_l;
       {
         const double nxl = fma(s, dx, ax), nyl = fma(s, dy, ay);
-        plain_l = (int)(((uint32_t)m & kFrozenBit) == 0) & (int)(s < rem) & (int)(s <= dsafe) &
-                  (int)((int)(nxl * inv_b) + 1 == abx) & (int)((int)(nyl * inv_b) + 1 == aby);
+        const int bxl = (int)(nxl * inv_b) + 2, byl = (int)(nyl * inv_b) + 2;
+        plain_l = (int)((m & kFrozenBit) == 0) & (int)(s < rem) & (int)(s <= dsafe) &
+                  (int)(nxl >= wlo) & (int)(nxl <= whi) & (int)(nyl >= wlo) & (int)(nyl <= whi);
+        nslot_l = byl * gridb + bxl;
         asm volatile("" : : "v"(plain_l));  // keep it here, beside the wave minimum
       }
       const unsigned key = argmin_key(s, valid);
@@ -867,25 +909,23 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         // end, or, where the window cannot vouch, a search of every slot);
         // the nearest disk's other values are read there only for a disk
         best_s = INFINITY;
-        wgid = 0xFFFFFFFFu;
+        wm = kFrozenBit;
         go = 0;
       } else {
       // the nearest disk
-      const int wls = argmin_lane(s, (uint32_t)m & ~kFrozenBit, key, key_min);
+      const int wls = argmin_lane_slots(s, m, own_gid, key, key_min);
       best_s = readlane_f64(s, wls);
-      const uint64_t mw = readlane_u64(m, wls);
-      wgid = (uint32_t)mw;
-      w_lidx = (int)(uint32_t)(mw >> 32);
+      wm = (uint32_t)readlane_i32((int)m, wls);
       wpx = readlane_f64(p.x, wls);
       wpy = readlane_f64(p.y, wls);
-      w_bx = wx0 + (wls & 3);
-      w_by = wy0 + ((wls >> 2) & 3);
+      w_bx = wx0 + (wls & 7);
+      w_by = wy0 + (wls >> 3);
       w_slot = readlane_i32(widx, wls);
 
       // the decision, made in vector registers and moved to the scalar unit once
 #define EC_DECIDE(CHECK_WINDOW)                                                     \
       do {                                                                          \
-        int kd = found ? ((wgid & kFrozenBit) ? EV_FROZEN : EV_LIFT) : 0;          \
+        int kd = found ? ((wm & kFrozenBit) ? EV_FROZEN : EV_LIFT) : 0;            \
         e = best_s;                                                                 \
         if (tx < e) { e = tx; kd = EV_WALL_X; }                                     \
         if (ty < e) { e = ty; kd = EV_WALL_Y; }                                     \
@@ -894,11 +934,11 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         nax = fma(step, dx, ax);                                                    \
         nay = fma(step, dy, ay);                                                    \
         /* bin of the moved centre, unclamped: a centre lies in [0, w], where    */ \
-        /* truncation gives bins 1..nb, and nb + 1 only on the far wall (or one  */ \
-        /* rounding past it); that case counts as a bin change and the general   */ \
-        /* path clamps it                                                       */ \
-        const int bx_ = (int)(nax * inv_b) + 1;                                     \
-        const int by_ = (int)(nay * inv_b) + 1;                                     \
+        /* truncation gives bins 2..nb+1, and nb + 2 only on the far wall (or    */ \
+        /* one rounding past it); that case counts as a bin change and the      */ \
+        /* general path clamps it                                               */ \
+        const int bx_ = (int)(nax * inv_b) + 2;                                     \
+        const int by_ = (int)(nay * inv_b) + 2;                                     \
         bool ok_ = true;                                                            \
         if (CHECK_WINDOW) ok_ = step <= dsafe;                                      \
         const int cr_ = (bx_ != abx || by_ != aby) ? 1 : 0;                          \
@@ -906,40 +946,41 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
                              ((ok_ ? 1 : 0) << 21) | (cr_ << 22));                  \
       } while (0)
       // The common event, a plain lift: the nearest disk (not frozen) is hit
-      // before either wall (a wall wins only when strictly nearer), chain
-      // length is left over, the window vouches for the move and the moved
-      // centre stays in its bin.  This is exactly the full decision
-      // (EC_DECIDE) finding such a lift; the general path makes the full
-      // decision for every other event.  All but the walls come from the
-      // winning lane's test above.
+      // within the remaining chain length, the window vouches for the move,
+      // and the moved centre stays inside the cell by the margin wmargin on
+      // both axes, so neither wall comes first (with the wall distance
+      // (wall - v) / d rounded as the full decision rounds it, a centre that
+      // stops wmargin short of the wall leaves the wall farther by far more
+      // than the rounding); the centre may change bin.  This is exactly the
+      // full decision (EC_DECIDE) finding such a lift; the general path makes
+      // the full decision for every other event.
       nax = fma(best_s, dx, ax);
       nay = fma(best_s, dy, ay);
-      {
-        int plain = readlane_i32(plain_l, wls);
-        // A moved centre that stays in a bin not bordering the wall ahead is
-        // at least one bin width short of that wall, a margin far beyond the
-        // rounding of the distances compared: only from the bins along the
-        // walls ahead can a wall come first.
-        if (__builtin_expect(abx == (xneg ? 1 : nb) || aby == (yneg ? 1 : nb), 0)) {
-          EC_WALLS();
-          plain &= uniform_i32((int)!(tx < best_s) & (int)!(ty < best_s));
-        }
-        go = (REJ == 0 && plain != 0) ? 1 : 0;  // else to the general path
-      }
+      const int nslot = readlane_i32(nslot_l, wls);
+      go = (REJ == 0 && readlane_i32(plain_l, wls) != 0) ? 1 : 0;  // else to the general path
       if (__builtin_expect(go != 0, 1)) {
         {
           const uint64_t sb = (uint64_t)__double_as_longlong(best_s);
-          // (the disk of a plain lift is not frozen: its id has no flag bit)
-          const uint32_t tag = ((uint32_t)EV_LIFT << 29) | wgid;
+          // (the disk of a plain lift is not frozen: its meta word is its own
+          // index, turned into its id when the records are hashed)
+          const uint32_t tag = ((uint32_t)EV_LIFT << 29) | wm;
           writelane3(rec_lo, rec_hi, rec_tag, (uint32_t)sb, (uint32_t)(sb >> 32), tag, n_ring);
         }
-        {
+        if (__builtin_expect(nslot == a_loc, 1)) {
           double2* const dst = (lane == 0) ? pos + a_loc : sink;
           *dst = make_double2(nax, nay);
+        } else {
+          // the moved centre crossed into another bin, which is empty (a bin
+          // holds one centre): lane 0 empties the old slot, lane 1 fills the
+          // new one, then lane 0 moves the meta word and lane 1 the slot index
+          double2* const dst = (lane == 0) ? pos + a_loc : ((lane == 1) ? pos + nslot : sink);
+          *dst = (lane == 0) ? nan2 : make_double2(nax, nay);
+          uint32_t* const dm = (lane == 0) ? meta + nslot : ((lane == 1) ? (uint32_t*)own_loc + a_lidx : sink32);
+          *dm = (lane == 0) ? (uint32_t)a_lidx : (uint32_t)nslot;
         }
         __builtin_amdgcn_wave_barrier();
         if (__builtin_expect(++n_ring == kDigestBatch, 0)) {
-          h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first);
+          h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first, own_gid);
           ring_first += kDigestBatch;
           n_ring = 0;
         }
@@ -947,8 +988,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         n_lift += 1;
         rem = rem - best_s;
         a_loc = w_slot;
-        a_gid = wgid;
-        a_lidx = w_lidx;
+        a_lidx = (int)wm;
         abx = w_bx;
         aby = w_by;
         ax = wpx;
@@ -985,22 +1025,21 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
           const double2 q2 = pos[sl];
           double s2;
           if (contact(q2.x - ax, q2.y - ay, dx, dy, sig2, s2)) {
-            const uint32_t i2 = (uint32_t)meta[sl] & ~kFrozenBit;
+            const uint32_t m2 = meta[sl];
+            const uint32_t i2 = (m2 & kFrozenBit) ? (m2 & ~kFrozenBit) : (uint32_t)own_gid[m2];
             if (s2 < ls || (s2 == ls && i2 < lid)) { ls = s2; lid = i2; lslot = sl; }
           }
         }
         const int fl = wave_argmin_all(ls, lid, lslot >= 0);
         found = fl >= 0 ? 1 : 0;
         best_s = INFINITY;
-        wgid = 0xFFFFFFFFu;
+        wm = kFrozenBit;
         if (fl >= 0) {
           best_s = readlane_f64(ls, fl);
           w_slot = readlane_i32(lslot, fl);
-          const uint64_t mw2 = meta[w_slot];
-          wgid = (uint32_t)uniform_i32((int)(uint32_t)mw2);
-          w_lidx = uniform_i32((int)(uint32_t)(mw2 >> 32));
-          w_bx = (w_slot >> 2) % gridb;
-          w_by = (w_slot >> 2) / gridb;
+          wm = (uint32_t)uniform_i32((int)meta[w_slot]);
+          w_bx = w_slot % gridb;
+          w_by = w_slot / gridb;
           // read into scalar registers here, so no load is left in flight
           // where this rare path rejoins the event path
           const double2 q2 = pos[w_slot];
@@ -1013,17 +1052,18 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
 #undef EC_WALLS
       const int kind = (packed >> 16) & 7;
       const bool ends = ((packed >> 20) & 1) != 0;
-      const int nbx = min(packed & 0xFF, nb), nby = min((packed >> 8) & 0xFF, nb);
+      const int nbx = min(packed & 0xFF, nb + 1), nby = min((packed >> 8) & 0xFF, nb + 1);
       // REJ 1: a wall or a frozen disk rejects the chain
       const bool rejected = REJ == 1 && !ends && kind != EV_LIFT;
       const double pax = ax, pay = ay;  // position before this event's move
       ax = nax;
       ay = nay;
-      // event record for the digest: bits of the step, kind << 32 | id
+      // event record for the digest: bits of the step, kind << 29 | id (an own
+      // disk by its own index, turned into its id when the records are hashed)
       const uint32_t eid = ends ? (uint32_t)end_id
                                 : (kind == EV_WALL_X ? (uint32_t)wall_x_id
                                                      : (kind == EV_WALL_Y ? (uint32_t)wall_y_id
-                                                                          : (wgid & ~kFrozenBit)));
+                                                                          : (wm & ~kFrozenBit)));
       {
         // lane n_ring keeps this event's record (lane writes, no change of
         // the execution mask)
@@ -1051,12 +1091,10 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
             const int2 sl = undo_slot[u];
             const double2 old = undo_pos[u];
             if (sl.y != sl.x) {
-              const uint64_t mv = meta[sl.y];
-              mask[sl.y >> 2] = mask[sl.y >> 2] & ~(1 << (sl.y & 3));
+              const uint32_t mv = meta[sl.y];
               pos[sl.y] = nan2;
-              mask[sl.x >> 2] = mask[sl.x >> 2] | (1 << (sl.x & 3));
               meta[sl.x] = mv;
-              own_loc[(int)(uint32_t)(mv >> 32)] = sl.x;
+              own_loc[(int)mv] = sl.x;
             }
             pos[sl.x] = old;
           }
@@ -1070,22 +1108,18 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         double2* const dst = (lane == 0) ? pos + a_loc : sink;
         *dst = make_double2(ax, ay);
       } else {
-        const int abin = aby * gridb + abx, nbin = nby * gridb + nbx;
-        const int nm = uniform_i32(mask[nbin]);
-        const int free_slot = __builtin_ctz((unsigned)(~nm & 0xF) | 0x10u);
-        if (__builtin_expect(free_slot >= 4, 0)) {
+        const int ns = nby * gridb + nbx;
+        const bool free_ = __builtin_isnan(readlane_f64(pos[ns].x, 0));
+        if (__builtin_expect(!free_, 0)) {
           if (lane == 0) {
             atomicOr(d.err, ERR_BIN_CAP);
             pos[a_loc] = make_double2(ax, ay);
           }
         } else {
-          const int ns = nbin * 4 + free_slot;
           if (lane == 0) {
-            mask[abin] = mask[abin] & ~(1 << (a_loc & 3));
             pos[a_loc] = nan2;
-            mask[nbin] = nm | (1 << free_slot);
             pos[ns] = make_double2(ax, ay);
-            meta[ns] = ((uint64_t)(uint32_t)a_lidx << 32) | a_gid;
+            meta[ns] = (uint32_t)a_lidx;
             own_loc[a_lidx] = ns;
           }
           a_loc = ns;
@@ -1099,7 +1133,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       }
       __builtin_amdgcn_wave_barrier();
       if (__builtin_expect(++n_ring == kDigestBatch, 0)) {
-        h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first);
+        h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first, own_gid);
         ring_first += kDigestBatch;
         n_ring = 0;
       }
@@ -1116,8 +1150,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         }
         rem = rem - e;
         a_loc = w_slot;
-        a_gid = wgid;
-        a_lidx = w_lidx;
+        a_lidx = (int)wm;
         abx = w_bx;
         aby = w_by;
         ax = wpx;
@@ -1176,7 +1209,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
           double* g = d.dbg;
           g[0] = (double)cell; g[1] = (double)k; g[2] = (double)sweep; g[3] = (double)q;
           g[4] = ax; g[5] = ay; g[6] = dx; g[7] = dy; g[8] = rem; g[9] = (double)a_loc;
-          g[10] = (double)a_gid; g[11] = (double)n_own;
+          g[10] = (double)own_gid[a_lidx]; g[11] = (double)n_own;
         }
       }
       aborted = 1;
@@ -1187,7 +1220,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
 
   // ---- write back: old position + local displacement, wrapped --------------
   wave_sync();
-  h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, n_ring, ring_first);
+  h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, n_ring, ring_first, own_gid);
   for (int k = lane; k < n_own; k += 64) {
     int g = own_gid[k];
     double2 v = pos[own_loc[k]];
