@@ -35,6 +35,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -62,11 +63,27 @@ SCATTER_BYTES_PER_DISK = 4 + 4
 # (256 CUs x 4 SIMDs), and a 64 x 64 grid admits at most 1024 non-adjacent cells
 CONCURRENT_CELLS = 1024
 CLOCK_GHZ = 2.4
-# HBM bytes of one sweep per disk (algorithmic): rebin reads x, y (16) and
-# writes/reads the cell index (8) and the id list (8); the four phases read
-# every disk once as its own (16 + 4 id) and write it back (16), and read the
-# frozen halo (about a quarter of the disks again, 20).
-HBM_BYTES_PER_DISK = 16 + 8 + 8 + 20 + 16 + 20
+# HBM bytes of one chain draw: start index (4) and direction (16), written by
+# the draw kernel and read by the simulation-cell kernel.
+CHAIN_DRAW_BYTES = 4 + 16
+
+
+def cell_kernel_bytes(n, eta, cells, chains):
+    """Algorithmic HBM bytes of one launch of the simulation-cell kernel
+    (all four colour phases of one sweep): every disk read once as its own
+    (id 4 + position 16) and written back (16), the frozen band -- the disks
+    within sigma outside a cell, a fraction ((w + 2 sigma)^2 - w^2) / w^2 of
+    all disks -- read again (id + position), and the chain draws read."""
+    w = math.sqrt(n * math.pi / (4.0 * eta)) / cells
+    band = ((w + 2.0) ** 2 - w * w) / (w * w)
+    return (20 + 16 + 20 * band) * n + CHAIN_DRAW_BYTES * chains
+
+
+def sweep_bytes(n, eta, cells, chains):
+    """Algorithmic HBM bytes of a whole sweep: the rebin kernels, the chain
+    draws written, and the simulation-cell kernel."""
+    return ((COUNT_BYTES_PER_DISK + SCATTER_BYTES_PER_DISK) * n + CHAIN_DRAW_BYTES * chains
+            + cell_kernel_bytes(n, eta, cells, chains))
 
 
 SCHEDULE_FLAGS = {"auto": lambda P: 0,
@@ -255,7 +272,9 @@ def main():
     events = counts["lifts"] + counts["frozen"] + counts["walls"] + counts["chains"]
     value = lifts / secs
     sweeps_s = args.steps / secs
-    hbm_frac = (HBM_BYTES_PER_DISK * w["n"] * sweeps_s) / (HBM_PEAK_GBS * 1e9)
+    chains_per_sweep = counts["chains"] / args.steps
+    hbm_frac = (sweep_bytes(w["n"], w["eta"], w["cells"], chains_per_sweep) * sweeps_s
+                / (HBM_PEAK_GBS * 1e9))
     avg_launch_s = phase_ms / 1e3 / max(launches, 1)
     # algorithmic FP64 work per launch: 100 flop per lift, the lifts of the
     # timed sweeps spread over the launches
@@ -314,9 +333,9 @@ def main():
                      "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VECTOR_PEAK_TF,
                      "traffic": traffic,
-                     "traffic_over_algorithmic": (traffic / (HBM_BYTES_PER_DISK * w["n"])
-                                                  if traffic is not None and kernel == "k_sweep_cells"
-                                                  else None),
+                     "traffic_over_algorithmic": (
+                         traffic / cell_kernel_bytes(w["n"], w["eta"], w["cells"], chains_per_sweep)
+                         if traffic is not None and kernel == "k_sweep_cells" else None),
                      "flop_per_lift": FLOP_PER_LIFT,
                      "lifts_per_launch": lifts / max(launches, 1),
                      "avg_launch_ms": avg_launch_s * 1e3, "launches": launches,
