@@ -818,11 +818,19 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     const double2 ap = pos[a_loc];
     double ax = ap.x, ay = ap.y;
     double rem = d.ell;
-    // event cap and abort polling: events left until the next poll, and polls
-    // made (the cap is a whole number of poll intervals, so it is met at a poll)
-    constexpr int kMaxPolls = (int)(kMaxEventsPerChain / kAbortPollEvents);
-    int poll_left = (int)kAbortPollEvents;
-    int n_polls = 0;
+    // event cap and abort polling, both at the digest flush (every 64 events
+    // of the cell): the error word loaded at the previous flush (or chain
+    // start) is read, the next load is issued, and the chain's event count,
+    // ring_first - ev0 at a flush, is held against the cap (so a chain makes
+    // at most kMaxEventsPerChain + 63 events)
+    const uint64_t ev0 = ring_first + (uint64_t)n_ring;
+    int capped = 0;
+#define EC_POLL()                                                                   \
+    do {                                                                            \
+      stop |= uniform_i32(nxt_err);                                                 \
+      nxt_err = load_err(d);                                                        \
+      capped = (ring_first - ev0 >= (uint64_t)kMaxEventsPerChain) ? 1 : 0;          \
+    } while (0)
     // REJ 1: the chain's undo log, contact sum and lifts (counted once accepted)
     int n_undo = 0;
     double chain_acc = 0.0;
@@ -834,19 +842,17 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     uint32_t m = meta[widx];
     int ended = 0;  // the chain length is used up
 
-    while (ended == 0 && stop == 0 && n_polls < kMaxPolls) {
+    while (ended == 0 && stop == 0 && capped == 0) {
       // the event found, and the decision (also read by the general path)
       double tx, ty, best_s, wpx, wpy, e, step, nax, nay;
       uint32_t wm;  // meta word of the nearest disk: own index, or id | frozen bit
       int w_bx, w_by, w_slot, packed;
-      int found;  // a disk can be hit (wave-uniform)
+      // (a disk can be hit exactly when best_s is finite)
       // Plain lifts run in this inner loop, where the direction and its
       // derived constants do not change: the general path, which can change
       // them, sits outside it, so the common event needs no register copies
-      // where the two paths would otherwise join.  The loop leaves on a
-      // uniform integer, tested after every event (go: 1 after a plain lift
-      // while no poll has stopped).
-      int go = 1;
+      // where the two paths would otherwise join.  The loop leaves as soon as
+      // an event is not a plain lift, or after a poll that stops the chain.
       // distances to the walls of the cell ahead: (wall - v) / d with 1/d
       // precomputed, clamped at 0
 #define EC_WALLS()                                                                  \
@@ -856,10 +862,11 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         ty = (wally - ay) * idyw;                                                   \
         ty = (ty < 0.0) ? 0.0 : ty;                                                 \
       } while (0)
-      // One plain-lift event (or, on any other event, the exit to the general
-      // path with go = 0); the loop runs two per pass, so that the common
-      // event takes a taken branch only every other time.
-      auto plain_event = [&]() __attribute__((always_inline)) {
+      // One plain-lift event; false on any other event (left to the general
+      // path) and after a poll that stops the chain.  The loop runs two per
+      // pass, so that the common event takes a taken branch only every other
+      // time; every return is a constant, so each exit is a plain branch.
+      auto plain_event = [&]() __attribute__((always_inline)) -> bool {
 
       // -- contact distance of the disk in this lane's window slot
       double s = 0.0;
@@ -903,15 +910,15 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       }
       const unsigned key = argmin_key(s, valid);
       const unsigned key_min = wave_min_u32(key);
-      found = key_min != 0xFFFFFFFFu ? 1 : 0;
-      if (__builtin_expect(found == 0, 0)) {
+      if (__builtin_expect(key_min == 0xFFFFFFFFu, 0)) {
         // no disk in the window: the general path decides (a wall, the chain
         // end, or, where the window cannot vouch, a search of every slot);
         // the nearest disk's other values are read there only for a disk
         best_s = INFINITY;
         wm = kFrozenBit;
-        go = 0;
-      } else {
+        return false;
+      }
+      {
       // the nearest disk
       const int wls = argmin_lane_slots(s, m, own_gid, key, key_min);
       best_s = readlane_f64(s, wls);
@@ -925,7 +932,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       // the decision, made in vector registers and moved to the scalar unit once
 #define EC_DECIDE(CHECK_WINDOW)                                                     \
       do {                                                                          \
-        int kd = found ? ((wm & kFrozenBit) ? EV_FROZEN : EV_LIFT) : 0;            \
+        int kd = (best_s < INFINITY) ? ((wm & kFrozenBit) ? EV_FROZEN : EV_LIFT) : 0; \
         e = best_s;                                                                 \
         if (tx < e) { e = tx; kd = EV_WALL_X; }                                     \
         if (ty < e) { e = ty; kd = EV_WALL_Y; }                                     \
@@ -957,8 +964,9 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       nax = fma(best_s, dx, ax);
       nay = fma(best_s, dy, ay);
       const int nslot = readlane_i32(nslot_l, wls);
-      go = (REJ == 0 && readlane_i32(plain_l, wls) != 0) ? 1 : 0;  // else to the general path
-      if (__builtin_expect(go != 0, 1)) {
+      // any other event goes to the general path
+      if (__builtin_expect(REJ == 1 || readlane_i32(plain_l, wls) == 0, 0)) return false;
+      {
         {
           const uint64_t sb = (uint64_t)__double_as_longlong(best_s);
           // (the disk of a plain lift is not frozen: its meta word is its own
@@ -966,24 +974,21 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
           const uint32_t tag = ((uint32_t)EV_LIFT << 29) | wm;
           writelane3(rec_lo, rec_hi, rec_tag, (uint32_t)sb, (uint32_t)(sb >> 32), tag, n_ring);
         }
-        if (__builtin_expect(nslot == a_loc, 1)) {
+        {
           double2* const dst = (lane == 0) ? pos + a_loc : sink;
           *dst = make_double2(nax, nay);
-        } else {
+        }
+        if (__builtin_expect(nslot != a_loc, 0)) {
           // the moved centre crossed into another bin, which is empty (a bin
-          // holds one centre): lane 0 empties the old slot, lane 1 fills the
-          // new one, then lane 0 moves the meta word and lane 1 the slot index
+          // holds one centre): lane 0 empties the old slot (over the store
+          // above: LDS stores of a wave land in order), lane 1 fills the new
+          // one, then lane 0 moves the meta word and lane 1 the slot index
           double2* const dst = (lane == 0) ? pos + a_loc : ((lane == 1) ? pos + nslot : sink);
           *dst = (lane == 0) ? nan2 : make_double2(nax, nay);
           uint32_t* const dm = (lane == 0) ? meta + nslot : ((lane == 1) ? (uint32_t*)own_loc + a_lidx : sink32);
           *dm = (lane == 0) ? (uint32_t)a_lidx : (uint32_t)nslot;
         }
         __builtin_amdgcn_wave_barrier();
-        if (__builtin_expect(++n_ring == kDigestBatch, 0)) {
-          h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first, own_gid);
-          ring_first += kDigestBatch;
-          n_ring = 0;
-        }
         acc = acc + fma(wpx - nax, dx, (wpy - nay) * dy);
         n_lift += 1;
         rem = rem - best_s;
@@ -997,22 +1002,22 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         widx = wbase + loff;
         p = pos[widx];
         m = meta[widx];
-        // event cap and abort polling (every value here is wave-uniform)
-        if (__builtin_expect(--poll_left == 0, 0)) {
-          poll_left = (int)kAbortPollEvents;
-          ++n_polls;
-          stop = uniform_i32(load_err(d));
-          go = (stop == 0 && n_polls < kMaxPolls) ? 1 : 0;
+        if (__builtin_expect(++n_ring == kDigestBatch, 0)) {
+          h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first, own_gid);
+          ring_first += kDigestBatch;
+          n_ring = 0;
+          EC_POLL();
+          if (stop != 0 || capped != 0) return false;
         }
       }
       }  // a disk in the window
+      return true;
       };
-      while (go != 0) {
-        plain_event();
-        if (__builtin_expect(go == 0, 0)) break;
-        plain_event();
+      for (;;) {
+        if (__builtin_expect(!plain_event(), 0)) break;
+        if (__builtin_expect(!plain_event(), 0)) break;
       }  // plain lifts
-      if (stop != 0 || n_polls >= kMaxPolls) continue;  // leaves the event loop
+      if (stop != 0 || capped != 0) continue;  // leaves the event loop
       {
       EC_WALLS();
       EC_DECIDE(true);
@@ -1031,7 +1036,6 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
           }
         }
         const int fl = wave_argmin_all(ls, lid, lslot >= 0);
-        found = fl >= 0 ? 1 : 0;
         best_s = INFINITY;
         wm = kFrozenBit;
         if (fl >= 0) {
@@ -1136,6 +1140,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first, own_gid);
         ring_first += kDigestBatch;
         n_ring = 0;
+        EC_POLL();
       }
       if (rejected) {
         ended = 1;
@@ -1194,13 +1199,8 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       p = pos[widx];
       m = meta[widx];
       }
-      // event cap and abort polling (every value here is wave-uniform)
-      if (__builtin_expect(--poll_left == 0, 0)) {
-        poll_left = (int)kAbortPollEvents;
-        ++n_polls;
-        stop = uniform_i32(load_err(d));
-      }
     }
+#undef EC_POLL
     if (ended == 0) {
       // stopped by another wave's error, or this chain reached the event cap
       if (stop == 0 && lane == 0) {
