@@ -132,7 +132,10 @@ typedef struct {
   double   eta;             /* 0 < eta < pi/(2 sqrt 3); L = sigma sqrt(N pi / (4 eta))       */
   double   ell;             /* displacement of one chain, > 0                               */
   int32_t  cells_per_side;  /* C: 1 = one periodic cell without walls; else even, >= 4,
-                               and cell side L/C > sigma                                    */
+                               and cell side L/C > sigma; a walled cell needs a side of at
+                               least 3 sigma and its LDS (20 B per bin of side < 0.7 sigma
+                               plus lists) within 160 KiB, about 54 sigma at most
+                               (EC_E_UNSUPPORTED outside)                                   */
   int32_t  chains_per_cell; /* <= 0: n_m = number of disks in the cell; > 0: fixed n_m      */
   int32_t  dir_mode;        /* ec_dir_mode                                                  */
   int32_t  precision;       /* ec_precision                                                 */

@@ -176,6 +176,10 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
     if (p->n_disks > (int64_t(1) << 29) - 4) {
       *why = "walled cells support at most 2^29 - 4 disks"; return EC_E_UNSUPPORTED;
     }
+    if (nb + 4 > 100) {  // the kernel's slot-to-bin division is exact up to here (the
+                         // LDS limit below is met first: about 87 bins per side)
+      *why = "internal: more than 100 bins per side"; return EC_E_UNSUPPORTED;
+    }
     out->w = w;
     out->nb = nb;
     out->cap_own = own_capacity(w, p->sigma);

@@ -298,6 +298,12 @@ __device__ __forceinline__ uint64_t digest_batch(uint32_t rec_lo, uint32_t rec_h
 
 enum { EV_LIFT = 1, EV_FROZEN = 2, EV_WALL_X = 3, EV_WALL_Y = 4, EV_PSEUDO = 5, EV_END = 6 };
 
+// Lifts among the first count event records held in the lanes.
+__device__ __forceinline__ uint32_t count_lifts(uint32_t rec_tag, int lane, int count) {
+  const bool is_lift = lane < count && (rec_tag >> 29) == (uint32_t)EV_LIFT;
+  return (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(is_lift));
+}
+
 // Contact distance of a disk moving along unit d towards a disk at offset r:
 // s = a - sqrt(sigma^2 - c^2) with a = r.d, c = r x d, for a > 0 and
 // sigma^2 - c^2 > 0; negative values (touching disks) become 0.
@@ -650,6 +656,14 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
   const double L = d.L, half_L = d.half_L, w = d.w, sigma = d.sigma, sig2 = d.sig2;
   const int gridb = d.gridb, nb = d.nb;
   const int nslots = gridb * gridb;  // one slot per bin
+  // bin coordinates of a slot: by = floor(slot / gridb) as (slot * m) >> 20
+  // with m = ceil(2^20 / gridb), exact for slot < gridb^2 when gridb^3 < 2^20
+  // (the host limits gridb to 100)
+  const uint32_t inv_g20 = ((1u << 20) + (uint32_t)gridb - 1u) / (uint32_t)gridb;
+  auto slot_bin = [&](int slot, int& bx, int& by) __attribute__((always_inline)) {
+    by = (int)(((uint32_t)slot * inv_g20) >> 20);
+    bx = slot - by * gridb;
+  };
 
   const CellLds lay = cell_lds_layout(gridb, d.cap_own, REJ == 1);
   double2* pos = (double2*)(base + lay.off_pos);
@@ -814,7 +828,6 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     EC_SET_DIRECTION();
     int a_loc = uniform_i32(own_loc[j]);
     int a_lidx = j;
-    int abx = a_loc % gridb, aby = a_loc / gridb;
     const double2 ap = pos[a_loc];
     double ax = ap.x, ay = ap.y;
     double rem = d.ell;
@@ -836,7 +849,11 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     double chain_acc = 0.0;
     uint32_t chain_lifts = 0;
     int wx0, wy0, wbase;
-    EC_WINDOW(abx, aby, xneg, yneg);
+    {
+      int bx0, by0;
+      slot_bin(a_loc, bx0, by0);
+      EC_WINDOW(bx0, by0, xneg, yneg);
+    }
     int widx = wbase + loff;  // this lane's slot in the window
     double2 p = pos[widx];
     uint32_t m = meta[widx];
@@ -990,20 +1007,18 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         }
         __builtin_amdgcn_wave_barrier();
         acc = acc + fma(wpx - nax, dx, (wpy - nay) * dy);
-        n_lift += 1;
         rem = rem - best_s;
         a_loc = w_slot;
         a_lidx = (int)wm;
-        abx = w_bx;
-        aby = w_by;
         ax = wpx;
         ay = wpy;
-        EC_WINDOW(abx, aby, xneg, yneg);
+        EC_WINDOW(w_bx, w_by, xneg, yneg);
         widx = wbase + loff;
         p = pos[widx];
         m = meta[widx];
         if (__builtin_expect(++n_ring == kDigestBatch, 0)) {
           h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first, own_gid);
+          if (REJ == 0) n_lift += count_lifts(rec_tag, lane, kDigestBatch);
           ring_first += kDigestBatch;
           n_ring = 0;
           EC_POLL();
@@ -1019,6 +1034,9 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       }  // plain lifts
       if (stop != 0 || capped != 0) continue;  // leaves the event loop
       {
+      // the mover's bin (the plain-lift loop carries only its slot)
+      int abx, aby;
+      slot_bin(a_loc, abx, aby);
       EC_WALLS();
       EC_DECIDE(true);
       if (__builtin_expect(((packed >> 21) & 1) == 0, 0)) {
@@ -1138,6 +1156,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       __builtin_amdgcn_wave_barrier();
       if (__builtin_expect(++n_ring == kDigestBatch, 0)) {
         h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first, own_gid);
+          if (REJ == 0) n_lift += count_lifts(rec_tag, lane, kDigestBatch);
         ring_first += kDigestBatch;
         n_ring = 0;
         EC_POLL();
@@ -1151,7 +1170,6 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
           chain_lifts += 1;
         } else {
           acc = acc + fma(wpx - ax, dx, (wpy - ay) * dy);
-          n_lift += 1;
         }
         rem = rem - e;
         a_loc = w_slot;
@@ -1221,6 +1239,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
   // ---- write back: old position + local displacement, wrapped --------------
   wave_sync();
   h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, n_ring, ring_first, own_gid);
+  if (REJ == 0) n_lift += count_lifts(rec_tag, lane, n_ring);
   for (int k = lane; k < n_own; k += 64) {
     int g = own_gid[k];
     double2 v = pos[own_loc[k]];

@@ -70,6 +70,23 @@ def test_invalid_parameters_rejected(kw, status):
     assert ei.value.status == status
 
 
+def test_walled_cell_side_limits():
+    """A walled cell's LDS (one 20-byte slot per bin of side < 0.7 sigma, plus
+    its lists) must fit 160 KiB: N = 68^2 in 4 x 4 cells is accepted at a
+    side of 54.3 sigma (eta = 0.077) and refused at 67.4 sigma (eta = 0.050)."""
+    import math
+    n, cells = 68 * 68, 4
+    for eta, ok in ((0.077, True), (0.050, False)):
+        w = math.sqrt(n * math.pi / (4.0 * eta)) / cells
+        assert (w < 55.0) == ok
+        if ok:
+            assert _ws(n=n, eta=eta, cells=cells) > 0
+        else:
+            with pytest.raises(E.ECError) as ei:
+                _ws(n=n, eta=eta, cells=cells)
+            assert ei.value.status == E.EC_E_UNSUPPORTED
+
+
 def test_abi_version_checked():
     p = P.make_params(65536, 0.70, 20.0, 16)
     p.abi_version = 99
