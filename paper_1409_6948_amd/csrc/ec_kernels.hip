@@ -811,7 +811,10 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
       wally = (dy > 0.0) ? w : ((dy < 0.0) ? 0.0 : INFINITY);                       \
       idxw = (dx != 0.0) ? idx : 1.0;                                               \
       idyw = (dy != 0.0) ? idy : 1.0;                                               \
-      dsafe = use_window ? reach / fmax(fabs(dx), fabs(dy)) : -1.0;                 \
+      /* reach / max(|dx|, |dy|) as reach * min(|1/dx|, |1/dy|) (a 0 component    */ \
+      /* has a factor 1, and then the other is +-1); a few ulps off, far below     */ \
+      /* the eps the reach keeps in hand, and only ever a guard                     */ \
+      dsafe = use_window ? reach * fmin(fabs(idxw), fabs(idyw)) : -1.0;             \
       xneg = uniform_i32(dx < 0.0 ? 1 : 0);                                         \
       yneg = uniform_i32(dy < 0.0 ? 1 : 0);                                         \
     } while (0)
@@ -1191,12 +1194,14 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
           const double rx = wpx - ax, ry = wpy - ay;
           acc = acc + fma(rx, dx, ry * dy);
           n_frozen += 1;
-          const double nrm = sqrt(fma(rx, rx, ry * ry));
+          // (both square roots are correctly rounded; their arguments, about
+          // sigma^2 and 1, lie in the range of sqrt_contact)
+          const double nrm = sqrt_contact(fma(rx, rx, ry * ry));
           const double nx = rx / nrm, ny = ry / nrm;
           const double dn = fma(dx, nx, dy * ny);
           const double tt = -2.0 * dn;
           const double ux = fma(tt, nx, dx), uy = fma(tt, ny, dy);
-          const double mm = sqrt(fma(ux, ux, uy * uy));
+          const double mm = sqrt_contact(fma(ux, ux, uy * uy));
           dx = ux / mm;
           dy = uy / mm;
           EC_SET_DIRECTION();
