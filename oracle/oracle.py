@@ -5,6 +5,7 @@ benchmark may import this module.  The product (the HIP library and its
 Python binding) never calls it.
 """
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -107,6 +108,15 @@ def philox(ctr, key):
 
 
 def lattice(p):
+    """The k x k start lattice (k = ceil(sqrt(N)); spacing a = L/k, odd rows
+    shifted by a/2).  Its nearest neighbours lie a apart, so it overlaps when
+    a < sigma (eta > pi/4 for N = k^2); such a start is refused, as the
+    library refuses it, since no chain could then make progress."""
+    k = int(math.ceil(math.sqrt(p.n)))
+    while k * k < p.n:
+        k += 1
+    if not box_length(p.n, p.sigma, p.eta) / k > p.sigma:
+        raise ValueError("start lattice spacing below sigma (eta > pi/4): the start would overlap")
     x = np.zeros(p.n, dtype=np.float64)
     y = np.zeros(p.n, dtype=np.float64)
     lib().orc_lattice(C.byref(p), _ptr(x, C.c_double), _ptr(y, C.c_double))

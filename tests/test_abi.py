@@ -52,6 +52,7 @@ def test_workspace_sizes_scale_with_n():
     (dict(n=0), E.EC_E_INVALID),
     (dict(eta=0.0), E.EC_E_INVALID),
     (dict(eta=0.91), E.EC_E_INVALID),
+    (dict(eta=0.80), E.EC_E_INVALID),                  # the start lattice overlaps above pi/4
     (dict(ell=0.0), E.EC_E_INVALID),
     (dict(cells=3), E.EC_E_INVALID),
     (dict(cells=2), E.EC_E_INVALID),

@@ -120,6 +120,39 @@ def test_walled_cells(P, n, eta, cells, ell, sweeps):
     _compare_full(P, n, eta, ell, cells, 1, sweeps, seed=7)
 
 
+@pytest.mark.parametrize("chains_per_cell", [0, 3])
+def test_walled_cells_with_empty_cells(P, chains_per_cell):
+    """N = 16 in 4 x 4 cells at eta = 0.05 (one disk per cell on average): on
+    the shifted grids of later sweeps some cells hold no disk and run no chain,
+    with n_m = n_c and with a fixed n_m = 3 alike (Sec. 3.4, step 5 draws
+    from the cell's own disks)."""
+    _compare_full(P, 16, 0.05, 5.0, 4, 1, 3, seed=7, chains_per_cell=chains_per_cell)
+    # the case does exercise empty cells (per-sweep chain tallies of the oracle)
+    st = O.State(O.params(16, 0.05, 5.0, 4, dir_mode=O.DIR_ISO, seed=7,
+                          chains_per_cell=chains_per_cell))
+    empty = 0
+    for _ in range(3):
+        before = st.acc_cnt[:, O.CNT_CHAINS].copy()
+        st.run(1)
+        empty += int(((st.acc_cnt[:, O.CNT_CHAINS] - before) == 0).sum())
+    assert empty > 0
+
+
+def test_tiny_chain_length(P):
+    """ell = 1e-7 sigma from the lattice at eta = 0.60: every chain is one
+    event, its end (a move of ell, no lift, no contact)."""
+    g, st = _compare_full(P, 1024, 0.60, 1e-7, 4, 1, 2, seed=7)
+    cnt = st.acc_cnt.sum(axis=0)
+    assert cnt[O.CNT_LIFTS] == 0 and cnt[O.CNT_FROZEN] == 0 and cnt[O.CNT_CHAINS] == 2 * 1024
+
+
+def test_near_jammed_lattice(P):
+    """eta = 0.78, just below pi/4, where the start lattice would overlap:
+    neighbours 0.35 % of sigma apart, about a thousand events per chain of
+    20 sigma: the densest start the lattice allows."""
+    _compare_full(P, 1024, 0.78, 20.0, 4, 1, 2, seed=7)
+
+
 @pytest.mark.parametrize("cpb", [1, 2, 4])
 def test_walled_cells_per_workgroup(P, cpb):
     _compare_full(P, 4096, 0.72, 20.0, 8, 1, 2, seed=8, cells_per_block=cpb)

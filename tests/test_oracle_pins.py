@@ -1073,3 +1073,28 @@ def test_stripes_two_disks_periodic_exact():
     f = np.array([np.histogram(rs[b * m:(b + 1) * m], bins=edges)[0] / m for b in range(B)])
     z = (f.mean(0) - exact) / (f.std(0, ddof=1) / math.sqrt(B))
     assert np.abs(z).max() < 4.5, z
+
+
+def test_start_lattice_nearest_neighbours_and_refusal():
+    """The start lattice (k x k sites, spacing a = L/k, odd rows shifted by
+    a/2) has its nearest neighbours exactly a apart: brute force over all
+    pairs with the minimum image, in numpy.  a = sigma sqrt(pi / (4 eta))
+    falls below sigma above eta = pi/4, and the oracle then refuses the start
+    (the library refuses it too), since the disks would overlap."""
+    n = 256
+    for eta in (0.50, 0.78):
+        p = O.params(n, eta, 1.0, 4)
+        x, y = O.lattice(p)
+        L = O.box_length(n, 1.0, eta)
+        dx = x[:, None] - x[None, :]
+        dy = y[:, None] - y[None, :]
+        dx -= L * np.round(dx / L)
+        dy -= L * np.round(dy / L)
+        r = np.sqrt(dx * dx + dy * dy)
+        np.fill_diagonal(r, np.inf)
+        a = L / 16
+        assert abs(r.min() - a) < 1e-12 * L
+        assert abs(a - math.sqrt(math.pi / (4.0 * eta))) < 1e-12
+        assert r.min() > 1.0
+    with pytest.raises(ValueError):
+        O.lattice(O.params(n, 0.80, 1.0, 4))
