@@ -55,10 +55,10 @@ FP64_VECTOR_PEAK_TF = 78.6     # MI355X FP64 vector, TFLOP/s
 # each) plus the commit (2 fma) = 8 * 12 + 4 = 100 flop.
 FLOP_PER_LIFT = 100.0
 # HBM bytes per disk of the two rebin kernels (algorithmic): the count kernel
-# reads x, y and writes the cell index; the scatter kernel reads the cell
-# index and writes the id into its cell's list.
-COUNT_BYTES_PER_DISK = 16 + 4
-SCATTER_BYTES_PER_DISK = 4 + 4
+# reads x, y and writes the cell index and the region (one byte); the scatter
+# kernel reads both and writes the id into its cell's list.
+COUNT_BYTES_PER_DISK = 16 + 4 + 1
+SCATTER_BYTES_PER_DISK = 4 + 1 + 4
 # simulation cells that can run at once on the chip: one wavefront per SIMD
 # (256 CUs x 4 SIMDs), and a 64 x 64 grid admits at most 1024 non-adjacent cells
 CONCURRENT_CELLS = 1024

@@ -19,7 +19,8 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 
 struct Layout {
-  size_t dev, sweep_ctr, x, y, cell_of, cell_ids, cell_count, cell_fill, cell_start, acc_delta, acc_cnt,
+  size_t dev, sweep_ctr, x, y, cell_of, reg_of, cell_ids, reg_count, reg_fill, cell_start, reg_start,
+      acc_delta, acc_cnt,
       ring, cell_digest, draws, err, red, chain_start, chain_dir, shuffle, dbg, psi, psi_part, psi_red,
       gr, queue, cell_done, psi_nb, psi_err, ovl, total;
 };
@@ -43,11 +44,14 @@ Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell, bool sweep_onl
   l.sweep_ctr = o;  o = align256(o + 8);
   l.x = o;          o = align256(o + 8 * no);
   l.y = o;          o = align256(o + 8 * no);
+  const size_t nr = (size_t)ec::kRegions * nc;
   l.cell_of = o;    o = align256(o + 4 * (size_t)n);
+  l.reg_of = o;     o = align256(o + (size_t)n);
   l.cell_ids = o;   o = align256(o + 4 * (size_t)n);
-  l.cell_count = o; o = align256(o + 4 * nc);
-  l.cell_fill = o;  o = align256(o + 4 * nc);
+  l.reg_count = o;  o = align256(o + 4 * nr);
+  l.reg_fill = o;   o = align256(o + 4 * nr);
   l.cell_start = o; o = align256(o + 4 * (nc + 1));
+  l.reg_start = o;  o = align256(o + 4 * (nr + 1));
   l.acc_delta = o;  o = align256(o + 8 * nc);
   l.acc_cnt = o;    o = align256(o + 8 * ec::CNT_NCOL * nc);
   l.ring = o;       o = align256(o + 8 * (size_t)ec::kDigestRing);
@@ -351,8 +355,10 @@ void fill_record(ec::Dev* out, const ec_params* p, const Derived& dv, unsigned c
   d.y = (double*)(b + lay.y);
   d.cell_of = (int32_t*)(b + lay.cell_of);
   d.cell_ids = (int32_t*)(b + lay.cell_ids);
-  d.cell_count = (int32_t*)(b + lay.cell_count);
-  d.cell_fill = (int32_t*)(b + lay.cell_fill);
+  d.reg_count = (int32_t*)(b + lay.reg_count);
+  d.reg_fill = (int32_t*)(b + lay.reg_fill);
+  d.reg_start = (int32_t*)(b + lay.reg_start);
+  d.reg_of = (uint8_t*)(b + lay.reg_of);
   d.cell_start = (int32_t*)(b + lay.cell_start);
   d.acc_delta = (double*)(b + lay.acc_delta);
   d.acc_cnt = (unsigned long long*)(b + lay.acc_cnt);
@@ -396,6 +402,10 @@ void fill_record(ec::Dev* out, const ec_params* p, const Derived& dv, unsigned c
   d.gridb = dv.nb + 4;  // own bins 2..nb+1, two rings of frozen-band bins around them
   d.b = dv.nb > 0 ? dv.w / (double)dv.nb : 0.0;
   d.inv_b = dv.nb > 0 ? 1.0 / d.b : 0.0;
+  // the cell's wall strips: sigma plus 1e-9 L, far above the few ulps of L by
+  // which two cells' local coordinates of one disk can disagree (w >= 3 sigma
+  // keeps the strips apart)
+  d.strip = p->sigma + 1e-9 * dv.L;
   d.margin = p->screen_margin > 0.0 ? p->screen_margin : 1e-5;  // relative to sigma
   d.cap_own = dv.cap_own;
   d.chains_per_cell = p->chains_per_cell;

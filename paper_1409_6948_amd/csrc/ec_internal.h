@@ -64,6 +64,9 @@ constexpr int kMaxGrBins = 1024;
 // Events hashed together, one per lane, by the walled-cell kernel's digest
 // (event ids then fit in 29 bits: N < 2^29 - 3).
 constexpr int kDigestBatch = 64;
+// regions of a cell: 3 x 3, r = 3 * ry + rx with rx, ry in {0: first strip,
+// 1: middle, 2: last strip}
+constexpr int kRegions = 9;
 // Rejection variant: lifts of one chain that can be undone (LDS log entries).
 constexpr int kUndoCap = 256;
 
@@ -72,11 +75,13 @@ constexpr int kUndoCap = 256;
 struct Dev {
   double* x;                        // [N] positions, disk-id order
   double* y;
-  int32_t* cell_count;              // [C*C]
-  int32_t* cell_fill;               // [C*C]
-  int32_t* cell_start;              // [C*C+1] exclusive prefix sum
+  int32_t* reg_count;               // [9*C*C] disks per (cell, region)
+  int32_t* reg_fill;                // [9*C*C]
+  int32_t* cell_start;              // [C*C+1] exclusive prefix sum over cells
+  int32_t* reg_start;               // [9*C*C+1] exclusive prefix sum over (cell, region)
   int32_t* cell_of;                 // [N]
-  int32_t* cell_ids;                // [N] ids grouped by cell (any order inside a cell)
+  uint8_t* reg_of;                  // [N] region of the disk in its cell (see k_count)
+  int32_t* cell_ids;                // [N] ids grouped by cell, by region inside a cell
   double* acc_delta;                // [C*C]
   unsigned long long* acc_cnt;      // [C*C*CNT_NCOL]
   unsigned long long* digest_ring;  // [kDigestRing]
@@ -101,6 +106,10 @@ struct Dev {
 
   int64_t n;
   double sigma, sig2, ell, L, half_L, w, cap, b, inv_b, margin;
+  // width of the wall strips that split a cell into 3 x 3 regions: sigma plus
+  // a margin far above the rounding of cell-local coordinates, so every disk a
+  // neighbour stages as frozen lies in the strips that face it
+  double strip;
   // FP32 screen (precision 1): error bounds of the FP32 contact terms against
   // the FP64 ones (a, sigma^2 - c^2, distance) and the threshold of
   // sigma^2 - c^2 above which the FP32 distance is within scr_e

@@ -394,10 +394,10 @@ __device__ int32_t decode_perm(uint64_t idx) {
 __global__ void k_prep(const Dev* __restrict__ ds, int squares) {
   const Dev& d = ds[blockIdx.y];
   const int64_t sweep = *d.sweep_ctr;
-  int ncell = d.C * d.C;
-  for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-    d.cell_count[c] = 0;
-    d.cell_fill[c] = 0;
+  const int nreg = kRegions * d.C * d.C;
+  for (int c = threadIdx.x; c < nreg; c += blockDim.x) {
+    d.reg_count[c] = 0;
+    d.reg_fill[c] = 0;
   }
   if (threadIdx.x == 0) {
     Stream st(d.seed, kKindSweep, (uint64_t)sweep, (uint64_t)d.system, 0);
@@ -428,12 +428,18 @@ __device__ __forceinline__ int cell_of_pos(const Dev& d, double px, double py, d
   return cy * d.C + cx;
 }
 
+// Region of a cell-local coordinate along one axis: 0 within the strip at the
+// cell's low wall, 2 within the strip at its high wall, 1 between.
+__device__ __forceinline__ int strip_of(double v, double w, double strip) {
+  return v < strip ? 0 : (v >= w - strip ? 2 : 1);
+}
+
 __global__ void k_count(const Dev* __restrict__ ds, int squares) {
   const Dev& d = ds[blockIdx.y];
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   SweepDraws dr = *d.draws;
-  int c;
+  int c, r = 0;  // cell and region (stripes and one periodic cell: region 0)
   if (d.stripes && !squares) {
     // stripe index from the coordinate across the stripes: horizontal stripes
     // (across = y) on even sweeps, vertical ones (across = x) on odd sweeps
@@ -442,20 +448,31 @@ __global__ void k_count(const Dev* __restrict__ ds, int squares) {
     if (c > d.C - 1) c = d.C - 1;
   } else {
     c = cell_of_pos(d, d.x[i], d.y[i], dr.sx, dr.sy);
+    if (d.C > 1) {
+      // the disk's region in its cell, from its cell-local coordinates (the
+      // wall strips are what neighbouring cells stage as their frozen band)
+      const int cx = c % d.C, cy = c / d.C;
+      const double vx = shifted(d.x[i], dr.sx, d.L) - (double)cx * d.w;
+      const double vy = shifted(d.y[i], dr.sy, d.L) - (double)cy * d.w;
+      r = 3 * strip_of(vy, d.w, d.strip) + strip_of(vx, d.w, d.strip);
+    }
   }
   d.cell_of[i] = c;
-  atomicAdd(&d.cell_count[c], 1);
+  d.reg_of[i] = (uint8_t)r;
+  atomicAdd(&d.reg_count[kRegions * c + r], 1);
 }
 
-// Exclusive prefix sum of the cell counts, one workgroup of 1024 threads.
+// Exclusive prefix sum of the (cell, region) counts, one workgroup of 1024
+// threads; a cell's start is that of its first region.
 __global__ void __launch_bounds__(1024) k_scan(const Dev* __restrict__ ds) {
   const Dev& d = ds[blockIdx.y];
   __shared__ int32_t part[1024];
-  int ncell = d.C * d.C;
-  int per = (ncell + 1023) / 1024;
+  const int ncell = d.C * d.C;
+  const int nreg = kRegions * ncell;
+  int per = (nreg + 1023) / 1024;
   int b0 = threadIdx.x * per;
   int sum = 0;
-  for (int c = b0; c < b0 + per && c < ncell; ++c) sum += d.cell_count[c];
+  for (int c = b0; c < b0 + per && c < nreg; ++c) sum += d.reg_count[c];
   part[threadIdx.x] = sum;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -465,20 +482,24 @@ __global__ void __launch_bounds__(1024) k_scan(const Dev* __restrict__ ds) {
     __syncthreads();
   }
   int run = (threadIdx.x == 0) ? 0 : part[threadIdx.x - 1];
-  for (int c = b0; c < b0 + per && c < ncell; ++c) {
-    d.cell_start[c] = run;
-    run += d.cell_count[c];
+  for (int c = b0; c < b0 + per && c < nreg; ++c) {
+    d.reg_start[c] = run;
+    if (c % kRegions == 0) d.cell_start[c / kRegions] = run;
+    run += d.reg_count[c];
   }
-  if (threadIdx.x == 1023) d.cell_start[ncell] = part[1023];
+  if (threadIdx.x == 1023) {
+    d.reg_start[nreg] = part[1023];
+    d.cell_start[ncell] = part[1023];
+  }
 }
 
 __global__ void k_scatter(const Dev* __restrict__ ds) {
   const Dev& d = ds[blockIdx.y];
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
-  int c = d.cell_of[i];
-  int slot = atomicAdd(&d.cell_fill[c], 1);
-  d.cell_ids[d.cell_start[c] + slot] = (int32_t)i;
+  const int k = kRegions * d.cell_of[i] + (int)d.reg_of[i];
+  int slot = atomicAdd(&d.reg_fill[k], 1);
+  d.cell_ids[d.reg_start[k] + slot] = (int32_t)i;
 }
 
 // ---------------------------------------------------------------------------
@@ -723,13 +744,25 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     own_loc[k] = s;
   }
   // frozen disks: centres of the 8 neighbouring cells within sigma of this
-  // cell, in the two outer rings of bins
+  // cell, in the two outer rings of bins.  Only a neighbour's regions that
+  // face this cell are read (its wall strips are wider than sigma, so they
+  // hold every such centre): the strip along the shared wall of an edge
+  // neighbour, the corner region of a diagonal one.  A region row is one
+  // range of the list, a region column three.
   for (int nbh = 0; nbh < 9; ++nbh) {
     if (nbh == 4) continue;
-    int ncx = (cx + (nbh % 3) - 1 + d.C) % d.C;
-    int ncy = (cy + (nbh / 3) - 1 + d.C) % d.C;
+    const int ox_ = nbh % 3 - 1, oy_ = nbh / 3 - 1;  // neighbour at (cx + ox_, cy + oy_)
+    int ncx = (cx + ox_ + d.C) % d.C;
+    int ncy = (cy + oy_ + d.C) % d.C;
     int nc = ncy * d.C + ncx;
-    int s0 = d.cell_start[nc], s1 = d.cell_start[nc + 1];
+    // its strips facing this cell: the low strip of a neighbour above or to
+    // the right, the high strip of one below or to the left, all three
+    // across an edge it shares
+    const int rx0 = ox_ > 0 ? 0 : (ox_ < 0 ? 2 : 0), rx1 = ox_ > 0 ? 0 : 2;
+    const int ry0 = oy_ > 0 ? 0 : (oy_ < 0 ? 2 : 0), ry1 = oy_ > 0 ? 0 : 2;
+    for (int ry = ry0; ry <= ry1; ++ry) {
+    const int k0 = kRegions * nc + 3 * ry;
+    int s0 = d.reg_start[k0 + rx0], s1 = d.reg_start[k0 + rx1 + 1];
     if (s0 < 0 || s1 < s0 || s1 - s0 > d.cap_own || (int64_t)s1 > d.n) {
       if (lane == 0) atomicOr(d.err, ERR_OWN_CAP);
       return;
@@ -750,6 +783,7 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
         pos[s] = make_double2(vx, vy);
       }
     }
+    }  // region rows
   }
   wave_sync();
   if (load_err(d) != 0) return;  // a capacity check failed somewhere: do not run chains
@@ -1245,6 +1279,16 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
   wave_sync();
   h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, n_ring, ring_first, own_gid);
   if (REJ == 0) n_lift += count_lifts(rec_tag, lane, n_ring);
+  // The cell's id list is sorted again by the regions of the moved disks:
+  // the neighbours of later colour phases stage their frozen band from the
+  // regions that face them.  The list keeps its range [start, start + n_own)
+  // (disks stay in their cell), and the region starts are rewritten; both
+  // are published with the positions.  LDS: the meta words are free now and
+  // hold the 9 region counts and the 9 fill cursors; own_loc takes each
+  // disk's region once its slot has been read.
+  uint32_t* const rcnt = meta;
+  if (lane < 2 * kRegions) rcnt[lane] = 0u;
+  wave_sync();
   for (int k = lane; k < n_own; k += 64) {
     int g = own_gid[k];
     double2 v = pos[own_loc[k]];
@@ -1257,6 +1301,25 @@ __device__ __forceinline__ void phase_cell(const Dev& d, const int64_t sweep, co
     if (ny < 0.0) ny += L; else if (ny >= L) ny -= L;
     d.x[g] = nx;
     d.y[g] = ny;
+    // (from the cell-local position, which differs from the one a neighbour
+    // computes from (nx, ny) by a few ulps of L, far inside the strip margin)
+    const int r = 3 * strip_of(v.y, w, d.strip) + strip_of(v.x, w, d.strip);
+    own_loc[k] = r;
+    atomicAdd(&rcnt[r], 1u);
+  }
+  wave_sync();
+  if (lane == 0) {
+    uint32_t run = (uint32_t)start;
+    for (int r = 0; r < kRegions; ++r) {
+      d.reg_start[kRegions * cell + r] = (int32_t)run;
+      rcnt[kRegions + r] = run;
+      run += rcnt[r];
+    }
+  }
+  wave_sync();
+  for (int k = lane; k < n_own; k += 64) {
+    const uint32_t at = atomicAdd(&rcnt[kRegions + own_loc[k]], 1u);
+    d.cell_ids[at] = own_gid[k];
   }
   if (lane == 0) {
     d.acc_delta[cell] = acc;
