@@ -79,6 +79,7 @@ Layout make_layout(int64_t n, int32_t C, int32_t chains_per_cell, bool sweep_onl
 struct Derived {
   double L, w;
   int32_t nb, cap_own, cpb, lds_per_cell;
+  int32_t pbins;  // one periodic cell: bins per side of its grid, 0 = brute force
   int32_t stripe_cap_own, stripe_cap_frozen, stripe_undo;  // striped decomposition only
 };
 
@@ -137,6 +138,21 @@ ec_status validate(const ec_params* p, Derived* out, std::string* why) {
       *why = "one periodic cell supports at most 2048 disks"; return EC_E_UNSUPPORTED;
     }
     out->w = L; out->nb = 0; out->cap_own = 0; out->cpb = 1; out->lds_per_cell = 0;
+    // The bin grid of the periodic cell: bins below 0.7 sigma (one centre
+    // each), at least 12 per side (the 8 x 8 window never meets itself), the
+    // window's reach 5b - sigma below the free-flight cap L/2 - sigma (a window
+    // event is then never a pseudo event), and the grid within 160 KiB of LDS;
+    // otherwise the brute-force search.
+    {
+      const double pb_side = 0.7 * p->sigma;
+      const double nbd = std::floor(L / pb_side) + 1.0;
+      const int32_t pb = nbd < 1000.0 ? (int32_t)nbd : 1000;
+      const double b = L / (double)pb;
+      const bool fits = pb >= 12 && pb <= 100 && b < pb_side && 2.0 * b > p->sigma &&
+                        5.0 * b < 0.5 * L &&
+                        ec::periodic_lds_layout(pb, (int)p->n_disks).bytes <= 160 * 1024;
+      out->pbins = fits ? pb : 0;
+    }
   } else if (p->flags & EC_FLAG_STRIPES) {
     if (C < 4 || (C & 1)) { *why = "the number of stripes must be even and >= 4"; return EC_E_INVALID; }
     if (p->dir_mode != EC_DIR_XY) {
@@ -312,6 +328,7 @@ ec::LaunchShape shape_of(const ec::Dev& d, const ec_params& p) {
   sh.max_chains = d.chains_per_cell > 0 ? (int64_t)d.C * d.C * d.chains_per_cell : d.n;
   sh.max_cells = d.C * d.C;
   sh.max_cells_side = d.C;
+  sh.pbins = d.C == 1 ? d.pbins : 0;
   sh.max_active = (d.C / 2) * (d.C / 2);
   sh.cpb = d.cells_per_block;
   sh.max_lds_per_cell = d.lds_per_cell;
@@ -400,6 +417,7 @@ void fill_record(ec::Dev* out, const ec_params* p, const Derived& dv, unsigned c
   d.C = p->cells_per_side;
   d.nb = dv.nb;
   d.gridb = dv.nb + 4;  // own bins 2..nb+1, two rings of frozen-band bins around them
+  d.pbins = dv.pbins;
   d.b = dv.nb > 0 ? dv.w / (double)dv.nb : 0.0;
   d.inv_b = dv.nb > 0 ? 1.0 / d.b : 0.0;
   // the cell's wall strips: sigma plus 1e-9 L, far above the few ulps of L by

@@ -115,6 +115,7 @@ struct Dev {
   // sigma^2 - c^2 above which the FP32 distance is within scr_e
   float scr_ea, scr_ed, scr_dg, scr_e;
   int32_t C, nb, gridb, cap_own, chains_per_cell, dir_mode, start_mode, precision;
+  int32_t pbins;  // one periodic cell: bins per side of its bin grid, 0 = brute-force search
   int32_t lds_per_cell, cells_per_block;
   int32_t search;                   // 0: 4x4-bin window with guard; 1: scan of every slot
   int64_t dep_wait_ticks;           // one-launch sweep: limit of one wait, 100 MHz clock ticks
@@ -152,6 +153,26 @@ __host__ __device__ inline CellLds cell_lds_layout(int gridb, int cap_own, bool 
   return l;
 }
 
+// LDS of the binned periodic cell: pbins x pbins slots (FP64 position, 32-bit
+// disk id), the slot of every disk, the shuffled start list, one sink slot
+// per lane.
+struct PeriodicLds {
+  int32_t off_pos, off_meta, off_slot_of, off_tmp, off_sink, bytes;
+};
+__host__ __device__ inline PeriodicLds periodic_lds_layout(int pbins, int n) {
+  PeriodicLds l;
+  const int slots = pbins * pbins;
+  int o = 0;
+  l.off_pos = o;      o += 16 * slots;
+  l.off_meta = o;     o += 4 * slots;
+  l.off_slot_of = o;  o += 4 * n;
+  l.off_tmp = o;      o += 4 * n;
+  o = (o + 15) & ~15;
+  l.off_sink = o;     o += 16 * 64;
+  l.bytes = o;
+  return l;
+}
+
 // LDS of one stripe in the striped-decomposition kernel: own disks (position
 // along and across the stripe, id, and a staging word), frozen disks
 // (along, across, id), and the undo log (disk, old position along).
@@ -179,6 +200,7 @@ struct LaunchShape {
   int64_t max_chains;       // chains per sweep
   int32_t max_cells;        // C * C
   int32_t max_cells_side;   // C (stripes: the number of stripes)
+  int32_t pbins;            // one periodic cell: bins per side (0: brute-force kernel)
   int32_t max_active;       // C * C / 4
   int32_t cpb;              // simulation cells per workgroup (same for all)
   int32_t max_lds_per_cell; // bytes

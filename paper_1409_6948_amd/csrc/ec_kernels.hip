@@ -288,7 +288,7 @@ __device__ __forceinline__ uint64_t digest_batch(uint32_t rec_lo, uint32_t rec_h
     const uint64_t sb = ((uint64_t)rec_hi << 32) | rec_lo;
     const int kind = (int)(rec_tag >> 29);
     uint32_t id = rec_tag & 0x1FFFFFFFu;
-    if (kind == 1) id = (uint32_t)own_gid[id];
+    if (kind == 1 && own_gid != nullptr) id = (uint32_t)own_gid[id];  // (null: ids as recorded)
     t = digest_term(kind, id, __longlong_as_double((long long)sb), first + (uint64_t)lane);
   }
   const uint32_t lo = (uint32_t)uniform_i32((int)wave_xor_all((uint32_t)t));
@@ -1922,6 +1922,249 @@ __global__ void k_zero_tallies(const Dev* __restrict__ ds) {
 }
 
 // The sweep counter every kernel of the next sweep reads (one thread per system).
+// ---------------------------------------------------------------------------
+// One periodic cell (C = 1) with a bin grid: the same events as k_periodic,
+// found in an 8 x 8-bin window around the moving disk as in the walled cells.
+// Bins of side b = L / pbins < 0.7 sigma hold one disk each (a slot: FP64
+// position, NaN when empty, and the disk's id); the window wraps around the
+// box, and each lane forms its disk's offset with the minimum image exactly
+// as k_periodic does, so the contact distances are the same numbers.  The
+// window reaches 2 bins behind the moving disk and 5 ahead along each axis,
+// so a move of length t with t max(|dx|, |dy|) <= 5b - sigma - eps keeps its
+// sigma-neighbourhood inside it; the host takes this kernel only where that
+// reach is below the free-flight cap L/2 - sigma, so a window event is never
+// a pseudo event.  Every other event (a longer flight, the chain end, the
+// cap) is decided as in k_periodic, over every slot when the window cannot
+// vouch.  Event records are kept in the lanes and hashed 64 at a time.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds) {
+  const Dev& d = ds[blockIdx.y];
+  const int64_t sweep = *d.sweep_ctr;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int lane = threadIdx.x;
+  const int n = (int)d.n;
+  const int nb = d.pbins;
+  const PeriodicLds lay = periodic_lds_layout(nb, n);
+  double2* const pos = (double2*)(lds_raw + lay.off_pos);
+  uint32_t* const meta = (uint32_t*)(lds_raw + lay.off_meta);
+  int32_t* const slot_of = (int32_t*)(lds_raw + lay.off_slot_of);
+  int32_t* const tmp = (int32_t*)(lds_raw + lay.off_tmp);
+  double2* const sink = (double2*)(lds_raw + lay.off_sink) + lane;
+  uint32_t* const sink32 = (uint32_t*)sink;
+  const int nslots = nb * nb;
+  const double L = d.L, half_L = d.half_L, sig2 = d.sig2, cap = d.cap, sigma = d.sigma;
+  const double b = L / (double)nb, inv_b = 1.0 / b;
+  const double2 nan2 = make_double2(__builtin_nan(""), __builtin_nan(""));
+  // bin coordinates of a slot: by = floor(slot / nb) as (slot * m) >> 20 with
+  // m = ceil(2^20 / nb), exact for slot < nb^2 when nb^3 < 2^20 (nb <= 100)
+  const uint32_t inv_n20 = ((1u << 20) + (uint32_t)nb - 1u) / (uint32_t)nb;
+  auto bin_of = [&](double v) __attribute__((always_inline)) {
+    int k = (int)(v * inv_b);
+    return k > nb - 1 ? nb - 1 : (k < 0 ? 0 : k);
+  };
+
+  for (int sl = lane; sl < nslots; sl += 64) {
+    pos[sl] = nan2;
+    meta[sl] = kEmptySlot;
+  }
+  wave_sync();
+  for (int i = lane; i < n; i += 64) {
+    const double x = d.x[i], y = d.y[i];
+    const int sl = bin_of(y) * nb + bin_of(x);
+    if (atomicCAS(&meta[sl], kEmptySlot, (uint32_t)i) != kEmptySlot) {
+      atomicOr(d.err, ERR_BIN_CAP);
+      continue;
+    }
+    pos[sl] = make_double2(x, y);
+    slot_of[i] = sl;
+  }
+  const int64_t n_m = d.chains_per_cell > 0 ? d.chains_per_cell : n;
+  if (d.start_mode == 1) {
+    wave_sync();
+    if (lane == 0) {
+      for (int i = 0; i < n; ++i) tmp[i] = i;
+      Stream st(d.seed, kKindShuffle, (uint64_t)sweep, cell_key(d, 0), 0);
+      for (int i = 0; i + 1 < n; ++i) {
+        int j = i + (int)draw_index(st, (uint64_t)(n - i));
+        int t = tmp[i]; tmp[i] = tmp[j]; tmp[j] = t;
+      }
+    }
+  }
+  wave_sync();
+  if (load_err(d) != 0) return;  // two disks in one bin: an overlap
+
+  double acc = d.acc_delta[0];
+  uint64_t n_lift = 0, n_pseudo = 0, h = 0;
+  int n_ring = 0;           // event records held in the lanes (lane k: record k)
+  uint64_t ring_first = 0;  // event index of record 0
+  uint32_t rec_lo = 0, rec_hi = 0, rec_tag = 0;
+  const int lx = lane & 7, ly = lane >> 3;
+  const double eps = 1e-9 * sigma;
+  const double reach = 5.0 * b - sigma - eps;
+  const uint32_t pseudo_id = (uint32_t)d.n + 2, end_id = (uint32_t)d.n + 3;
+  // one event record; the records are hashed 64 at a time
+  auto record = [&](int kind, uint32_t id, double step) __attribute__((always_inline)) {
+    const uint64_t sb = (uint64_t)__double_as_longlong(step);
+    writelane3(rec_lo, rec_hi, rec_tag, (uint32_t)sb, (uint32_t)(sb >> 32),
+               ((uint32_t)kind << 29) | id, n_ring);
+    if (++n_ring == kDigestBatch) {
+      h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first, nullptr);
+      ring_first += kDigestBatch;
+      n_ring = 0;
+    }
+  };
+
+  for (int64_t k = 0; k < n_m; ++k) {
+    int a;
+    if (d.start_mode == 1) {
+      a = tmp[k % n];
+    } else {
+      Stream st(d.seed, kKindStart, (uint64_t)sweep, cell_key(d, 0), (uint64_t)k);
+      a = (int)draw_index(st, (uint64_t)n);
+    }
+    double dx, dy;
+    chain_direction(d, sweep, 0, k, dx, dy);
+    // reach / max(|dx|, |dy|) from the reciprocals (a 0 component has a factor 1)
+    const double rx_ = dx != 0.0 ? 1.0 / dx : 1.0, ry_ = dy != 0.0 ? 1.0 / dy : 1.0;
+    const double dsafe = reach * fmin(fabs(rx_), fabs(ry_));
+    const int offx = dx < 0.0 ? -5 : -2, offy = dy < 0.0 ? -5 : -2;  // window origin
+    double rem = d.ell;
+    int a_slot = uniform_i32(slot_of[a]);
+    double ax = pos[a_slot].x, ay = pos[a_slot].y;
+    int64_t n_events = 0;
+    for (;;) {
+      if (++n_events > kMaxEventsPerChain) {
+        if (lane == 0) atomicOr(d.err, ERR_EVENT_CAP);
+        break;
+      }
+      // the 8 x 8-bin window, wrapped around the box
+      int abx, aby;
+      aby = (int)(((uint32_t)a_slot * inv_n20) >> 20);
+      abx = a_slot - aby * nb;
+      int wx = abx + offx + lx, wy = aby + offy + ly;
+      wx += wx < 0 ? nb : 0;
+      wx -= wx >= nb ? nb : 0;
+      wy += wy < 0 ? nb : 0;
+      wy -= wy >= nb ? nb : 0;
+      const int wsl = wy * nb + wx;
+      const double2 p = pos[wsl];
+      const uint32_t m = meta[wsl];
+      double rx = p.x - ax, ry = p.y - ay;
+      if (rx < -half_L) rx += L; else if (rx >= half_L) rx -= L;
+      if (ry < -half_L) ry += L; else if (ry >= half_L) ry -= L;
+      double s = 0.0;
+      const bool valid = contact(rx, ry, dx, dy, sig2, s);  // the mover's own slot: no contact
+      const unsigned key = argmin_key(s, valid);
+      const unsigned key_min = wave_min_u32(key);
+      double best_s = INFINITY, wpx = 0.0, wpy = 0.0;
+      int bj = -1, bslot = -1;
+      if (key_min != 0xFFFFFFFFu) {
+        const int wl = argmin_lane(s, m, key, key_min);
+        best_s = readlane_f64(s, wl);
+        bj = readlane_i32((int)m, wl);
+        bslot = readlane_i32(wsl, wl);
+        wpx = readlane_f64(p.x, wl);
+        wpy = readlane_f64(p.y, wl);
+      }
+      if (!(best_s <= dsafe)) {
+        // the window cannot vouch: the nearest contact over every slot
+        double ls = INFINITY;
+        uint32_t lid = 0xFFFFFFFFu;
+        int lsl = -1;
+        for (int sl = lane; sl < nslots; sl += 64) {
+          const double2 q = pos[sl];
+          double qx = q.x - ax, qy = q.y - ay;
+          if (qx < -half_L) qx += L; else if (qx >= half_L) qx -= L;
+          if (qy < -half_L) qy += L; else if (qy >= half_L) qy -= L;
+          double s2;
+          if (contact(qx, qy, dx, dy, sig2, s2)) {
+            const uint32_t i2 = meta[sl];
+            if (s2 < ls || (s2 == ls && i2 < lid)) { ls = s2; lid = i2; lsl = sl; }
+          }
+        }
+        const int fl = wave_argmin_all(ls, lid, lsl >= 0);
+        best_s = INFINITY;
+        bj = -1;
+        if (fl >= 0) {
+          best_s = readlane_f64(ls, fl);
+          bj = readlane_i32((int)lid, fl);
+          bslot = readlane_i32(lsl, fl);
+          const double2 q = pos[bslot];
+          wpx = readlane_f64(q.x, 0);
+          wpy = readlane_f64(q.y, 0);
+        }
+      }
+      // the event, in the order k_periodic decides it
+      const double lim = best_s < rem ? best_s : rem;
+      double step;
+      int kind;
+      if (lim > cap) {
+        step = cap; kind = EV_PSEUDO;
+        record(EV_PSEUDO, pseudo_id, cap);
+      } else if (!(best_s < rem)) {
+        step = rem; kind = EV_END;
+        record(EV_END, end_id, rem);
+      } else {
+        step = best_s; kind = EV_LIFT;
+        record(EV_LIFT, (uint32_t)bj, best_s);
+      }
+      double nax = fma(step, dx, ax), nay = fma(step, dy, ay);
+      if (nax >= L) nax -= L; else if (nax < 0.0) nax += L;
+      if (nay >= L) nay -= L; else if (nay < 0.0) nay += L;
+      // store the moved disk (lane 0) and move it to another bin if it crossed
+      // one (lane 0 empties the old slot, lane 1 fills the new one, which is
+      // empty: a bin holds one centre)
+      const int ns = bin_of(nay) * nb + bin_of(nax);
+      {
+        double2* const dst = (lane == 0) ? pos + a_slot : sink;
+        *dst = make_double2(nax, nay);
+      }
+      if (ns != a_slot) {
+        double2* const dst = (lane == 0) ? pos + a_slot : ((lane == 1) ? pos + ns : sink);
+        *dst = (lane == 0) ? nan2 : make_double2(nax, nay);
+        uint32_t* const dm = (lane == 0) ? meta + a_slot : ((lane == 1) ? meta + ns : sink32);
+        *dm = (lane == 0) ? kEmptySlot : (uint32_t)a;
+        if (lane == 0) slot_of[a] = ns;
+        a_slot = ns;
+      }
+      wave_sync();
+      if (kind == EV_END) break;
+      if (kind == EV_PSEUDO) {
+        rem = rem - cap;
+        n_pseudo += 1;
+        ax = nax;
+        ay = nay;
+        continue;
+      }
+      rem = rem - best_s;
+      double tx = wpx - nax, ty = wpy - nay;
+      if (tx < -half_L) tx += L; else if (tx >= half_L) tx -= L;
+      if (ty < -half_L) ty += L; else if (ty >= half_L) ty -= L;
+      acc = acc + fma(tx, dx, ty * dy);
+      n_lift += 1;
+      a = bj;
+      a_slot = bslot;
+      ax = wpx;
+      ay = wpy;
+    }
+  }
+  wave_sync();
+  h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, n_ring, ring_first, nullptr);
+  for (int i = lane; i < n; i += 64) {
+    const double2 v = pos[slot_of[i]];
+    d.x[i] = v.x;
+    d.y[i] = v.y;
+  }
+  if (lane == 0) {
+    d.acc_delta[0] = acc;
+    d.acc_cnt[CNT_LIFTS] += n_lift;
+    d.acc_cnt[CNT_CHAINS] += (uint64_t)n_m;
+    d.acc_cnt[CNT_PSEUDO] += n_pseudo;
+    d.digest_ring[sweep % kDigestRing] = h;
+    d.cell_digest[0] = h;
+  }
+}
+
 __global__ void k_sweep_done(const Dev* __restrict__ ds) {
   if (threadIdx.x == 0) *ds[blockIdx.y].sweep_ctr += 1;
 }
@@ -1947,11 +2190,12 @@ hipError_t launch_zero_tallies(const Dev* ds, int32_t n_cells, hipStream_t st) {
 }
 
 hipError_t set_phase_lds_limit(int bytes) {
-  const void* fns[10] = {(const void*)k_phase<0, 0>,       (const void*)k_phase<1, 0>,
+  const void* fns[11] = {(const void*)k_phase<0, 0>,       (const void*)k_phase<1, 0>,
                          (const void*)k_phase<0, 1>,       (const void*)k_sweep_cells<0, 0>,
                          (const void*)k_sweep_cells<1, 0>, (const void*)k_sweep_cells<0, 1>,
                          (const void*)k_queue_cells<0, 0>, (const void*)k_queue_cells<1, 0>,
-                         (const void*)k_queue_cells<0, 1>, (const void*)k_stripe_phase<0>};
+                         (const void*)k_queue_cells<0, 1>, (const void*)k_stripe_phase<0>,
+                         (const void*)k_periodic_bins};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -1981,9 +2225,14 @@ hipError_t launch_sweep(const Dev* ds, const LaunchShape& sh, hipStream_t st,
                         const PhaseEvents* ev) {
   const unsigned ns = (unsigned)sh.n_sys;
   if (sh.periodic) {
-    size_t lds = (size_t)sh.max_n * 16 + (size_t)sh.max_n * 4;
     if (ev) (void)hipEventRecord(ev->begin[0], st);
-    hipLaunchKernelGGL(k_periodic, dim3(1, ns), dim3(64), lds, st, ds);
+    if (sh.pbins > 0) {
+      const size_t lds = (size_t)periodic_lds_layout(sh.pbins, (int)sh.max_n).bytes;
+      hipLaunchKernelGGL(k_periodic_bins, dim3(1, ns), dim3(64), lds, st, ds);
+    } else {
+      const size_t lds = (size_t)sh.max_n * 16 + (size_t)sh.max_n * 4;
+      hipLaunchKernelGGL(k_periodic, dim3(1, ns), dim3(64), lds, st, ds);
+    }
     if (ev) (void)hipEventRecord(ev->end[0], st);
     hipError_t e = launch_check_overlap(ds, sh, st);
     if (e != hipSuccess) return e;
