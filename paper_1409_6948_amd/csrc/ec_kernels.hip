@@ -1958,6 +1958,12 @@ __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds
   // bin coordinates of a slot: by = floor(slot / nb) as (slot * m) >> 20 with
   // m = ceil(2^20 / nb), exact for slot < nb^2 when nb^3 < 2^20 (nb <= 100)
   const uint32_t inv_n20 = ((1u << 20) + (uint32_t)nb - 1u) / (uint32_t)nb;
+  // the minimum image of an offset, as k_periodic forms it (v + L below
+  // -L/2, v - L from L/2 on), written as selects so that no lane branches
+  auto min_image = [&](double v) __attribute__((always_inline)) {
+    const double vp = v + L, vm = v - L;
+    return v < -half_L ? vp : (v >= half_L ? vm : v);
+  };
   auto bin_of = [&](double v) __attribute__((always_inline)) {
     int k = (int)(v * inv_b);
     return k > nb - 1 ? nb - 1 : (k < 0 ? 0 : k);
@@ -2022,8 +2028,13 @@ __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds
       Stream st(d.seed, kKindStart, (uint64_t)sweep, cell_key(d, 0), (uint64_t)k);
       a = (int)draw_index(st, (uint64_t)n);
     }
+    // every lane draws the same values; read them as one (scalar) value so
+    // that every decision below is a uniform branch
+    a = uniform_i32(a);
     double dx, dy;
     chain_direction(d, sweep, 0, k, dx, dy);
+    dx = readlane_f64(dx, 0);
+    dy = readlane_f64(dy, 0);
     // reach / max(|dx|, |dy|) from the reciprocals (a 0 component has a factor 1)
     const double rx_ = dx != 0.0 ? 1.0 / dx : 1.0, ry_ = dy != 0.0 ? 1.0 / dy : 1.0;
     const double dsafe = reach * fmin(fabs(rx_), fabs(ry_));
@@ -2049,9 +2060,7 @@ __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds
       const int wsl = wy * nb + wx;
       const double2 p = pos[wsl];
       const uint32_t m = meta[wsl];
-      double rx = p.x - ax, ry = p.y - ay;
-      if (rx < -half_L) rx += L; else if (rx >= half_L) rx -= L;
-      if (ry < -half_L) ry += L; else if (ry >= half_L) ry -= L;
+      const double rx = min_image(p.x - ax), ry = min_image(p.y - ay);
       double s = 0.0;
       const bool valid = contact(rx, ry, dx, dy, sig2, s);  // the mover's own slot: no contact
       const unsigned key = argmin_key(s, valid);
@@ -2066,16 +2075,14 @@ __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds
         wpx = readlane_f64(p.x, wl);
         wpy = readlane_f64(p.y, wl);
       }
-      if (!(best_s <= dsafe)) {
+      if (uniform_i32(best_s <= dsafe ? 0 : 1) != 0) {
         // the window cannot vouch: the nearest contact over every slot
         double ls = INFINITY;
         uint32_t lid = 0xFFFFFFFFu;
         int lsl = -1;
         for (int sl = lane; sl < nslots; sl += 64) {
           const double2 q = pos[sl];
-          double qx = q.x - ax, qy = q.y - ay;
-          if (qx < -half_L) qx += L; else if (qx >= half_L) qx -= L;
-          if (qy < -half_L) qy += L; else if (qy >= half_L) qy -= L;
+          const double qx = min_image(q.x - ax), qy = min_image(q.y - ay);
           double s2;
           if (contact(qx, qy, dx, dy, sig2, s2)) {
             const uint32_t i2 = meta[sl];
@@ -2094,27 +2101,18 @@ __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds
           wpy = readlane_f64(q.y, 0);
         }
       }
-      // the event, in the order k_periodic decides it
+      // the event, in the order k_periodic decides it (one scalar value)
       const double lim = best_s < rem ? best_s : rem;
-      double step;
-      int kind;
-      if (lim > cap) {
-        step = cap; kind = EV_PSEUDO;
-        record(EV_PSEUDO, pseudo_id, cap);
-      } else if (!(best_s < rem)) {
-        step = rem; kind = EV_END;
-        record(EV_END, end_id, rem);
-      } else {
-        step = best_s; kind = EV_LIFT;
-        record(EV_LIFT, (uint32_t)bj, best_s);
-      }
+      const int kind = uniform_i32(lim > cap ? EV_PSEUDO : (!(best_s < rem) ? EV_END : EV_LIFT));
+      const double step = kind == EV_PSEUDO ? cap : (kind == EV_END ? rem : best_s);
+      record(kind, kind == EV_PSEUDO ? pseudo_id : (kind == EV_END ? end_id : (uint32_t)bj), step);
       double nax = fma(step, dx, ax), nay = fma(step, dy, ay);
       if (nax >= L) nax -= L; else if (nax < 0.0) nax += L;
       if (nay >= L) nay -= L; else if (nay < 0.0) nay += L;
       // store the moved disk (lane 0) and move it to another bin if it crossed
       // one (lane 0 empties the old slot, lane 1 fills the new one, which is
       // empty: a bin holds one centre)
-      const int ns = bin_of(nay) * nb + bin_of(nax);
+      const int ns = uniform_i32(bin_of(nay) * nb + bin_of(nax));
       {
         double2* const dst = (lane == 0) ? pos + a_slot : sink;
         *dst = make_double2(nax, nay);
