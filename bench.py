@@ -224,7 +224,11 @@ def main():
     flags = SCHEDULE_FLAGS[args.schedule](P)
     kernel = "k_phase" if args.schedule == "phase-launches" else "k_sweep_cells"
     if w["cells"] == 1:
-        kernel = "k_periodic"  # one periodic cell: N serial chains in one wavefront
+        # one periodic cell: N serial chains in one wavefront, on the bin grid
+        # where the box holds at least 12 bins below 0.7 sigma per side (the
+        # library's rule; the label only names the kernel that is timed)
+        box = math.sqrt(w["n"] * math.pi / (4.0 * w["eta"]))
+        kernel = "k_periodic_bins" if math.floor(box / 0.7) + 1 >= 12 else "k_periodic"
     p = P.make_params(w["n"], w["eta"], w["ell"], w["cells"], dir_mode=w["dir_mode"],
                       seed=w["seed"], cells_per_block=args.cells_per_block, precision=prec,
                       flags=flags)
@@ -317,7 +321,8 @@ def main():
                    "cells_per_side": w["cells"], "ell": w["ell"],
                    "directions": "isotropic" if w["dir_mode"] == 1 else "+x/+y alternating",
                    "precision": precision,
-                   "schedule": {"k_phase": "phase-launches", "k_periodic": "one periodic cell"}.get(
+                   "schedule": {"k_phase": "phase-launches", "k_periodic": "one periodic cell",
+                                "k_periodic_bins": "one periodic cell"}.get(
                        kernel, "one-launch"),
                    "start": "lattice",
                    "sweeps_before_timing": args.warmup},
