@@ -288,8 +288,23 @@ __device__ __forceinline__ uint64_t digest_batch(uint32_t rec_lo, uint32_t rec_h
     const uint64_t sb = ((uint64_t)rec_hi << 32) | rec_lo;
     const int kind = (int)(rec_tag >> 29);
     uint32_t id = rec_tag & 0x1FFFFFFFu;
-    if (kind == 1 && own_gid != nullptr) id = (uint32_t)own_gid[id];  // (null: ids as recorded)
+    if (kind == 1) id = (uint32_t)own_gid[id];
     t = digest_term(kind, id, __longlong_as_double((long long)sb), first + (uint64_t)lane);
+  }
+  const uint32_t lo = (uint32_t)uniform_i32((int)wave_xor_all((uint32_t)t));
+  const uint32_t hi = (uint32_t)uniform_i32((int)wave_xor_all((uint32_t)(t >> 32)));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// The same hash of records whose ids are the disks' own (no index to turn
+// into an id): the periodic cell's records.
+__device__ __forceinline__ uint64_t digest_batch_ids(uint32_t rec_lo, uint32_t rec_hi, uint32_t rec_tag,
+                                                     int lane, int count, uint64_t first) {
+  uint64_t t = 0;
+  if (lane < count) {
+    const uint64_t sb = ((uint64_t)rec_hi << 32) | rec_lo;
+    t = digest_term((int)(rec_tag >> 29), rec_tag & 0x1FFFFFFFu,
+                    __longlong_as_double((long long)sb), first + (uint64_t)lane);
   }
   const uint32_t lo = (uint32_t)uniform_i32((int)wave_xor_all((uint32_t)t));
   const uint32_t hi = (uint32_t)uniform_i32((int)wave_xor_all((uint32_t)(t >> 32)));
@@ -2014,7 +2029,7 @@ __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds
     writelane3(rec_lo, rec_hi, rec_tag, (uint32_t)sb, (uint32_t)(sb >> 32),
                ((uint32_t)kind << 29) | id, n_ring);
     if (++n_ring == kDigestBatch) {
-      h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first, nullptr);
+      h ^= digest_batch_ids(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first);
       ring_first += kDigestBatch;
       n_ring = 0;
     }
@@ -2147,7 +2162,7 @@ __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds
     }
   }
   wave_sync();
-  h ^= digest_batch(rec_lo, rec_hi, rec_tag, lane, n_ring, ring_first, nullptr);
+  h ^= digest_batch_ids(rec_lo, rec_hi, rec_tag, lane, n_ring, ring_first);
   for (int i = lane; i < n; i += 64) {
     const double2 v = pos[slot_of[i]];
     d.x[i] = v.x;
