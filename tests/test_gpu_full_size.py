@@ -7,7 +7,9 @@ sample of cells of every phase together with their dependency cones (the
 earlier-phase neighbours, recursively) from the positions at the start of the
 sweep, which reproduces those cells exactly; positions, per-cell tallies and
 per-cell event digests must then equal the device's bit for bit.  Sweep 1 is
-replayed from the device's positions and tallies after sweep 0.  The 65k
+replayed from the device's positions and tallies after sweep 0, and a late
+sweep (the 25th at 1M disks, in both precisions; the 4th at 16.7M disks in
+the FP32-screened form) from the device's state before it.  The 65k
 workload is compared whole, every cell, over three sweeps.  Every
 configuration is checked for overlaps with the oracle's pair search.
 """
@@ -122,6 +124,37 @@ def test_full_size_cones_of_every_phase_two_sweeps(P, name):
     for xy in (s1[:2], s2[:2]):
         d, i, j = O.min_pair_distance(xy[0], xy[1], L, r_cut=1.0 - 1e-12)
         assert d == np.inf, (d, i, j)
+
+
+@pytest.mark.parametrize("name,precision,late", [
+    ("pec_1m", 0, 24),
+    ("pec_1m", 1, 24),
+    ("pec_16m", 1, 3),
+])
+def test_cones_of_a_late_sweep(P, name, precision, late):
+    """Far from the lattice start: after `late` device sweeps the oracle
+    replays cones of every colour phase of the next sweep from the device's
+    positions and tallies.  The FP32-screened form (precision 1, the form of
+    the 16.7M configuration, with its chain length 30 sigma) must give the
+    events of the FP64 oracle."""
+    w = inputs.WORKLOADS[name]
+    n, eta, C, ell = w["n"], w["eta"], w["cells"], w["ell"]
+    _say(f"[late sweep] {name}: precision={precision} n={n} eta={eta} C={C} ell={ell}: "
+         f"{late} + 1 GPU sweeps, device overlap check on")
+    g = P.System(P.make_params(n, eta, ell, C, seed=w["seed"], precision=precision,
+                               flags=P.EC_FLAG_CHECK_OVERLAP))
+    g.sweep(late)
+    s0 = _gpu_state(g)
+    g.sweep(1)
+    s1 = _gpu_state(g)
+    assert g.sweep_count() == late + 1
+    g.close()
+    p = O.params(n, eta, ell, C, dir_mode=O.DIR_ISO, seed=w["seed"])
+    targets = _sample_targets(C, O.sweep_draws(p, late)[2], 4, seed=late)
+    _say(f"[late sweep] {name}: sweep {late}: oracle replay of 4 cells per phase and their cones")
+    k = _replay_and_compare(p, late, s0[:2], (s0[2], s0[3]), s1, targets)
+    _say(f"[late sweep] {name}: sweep {late}: {k} cells equal")
+    assert int(s1[3][:, O.CNT_CHAINS].sum()) == (late + 1) * n
 
 
 def test_pec_65k_three_whole_sweeps(P):

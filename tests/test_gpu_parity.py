@@ -80,9 +80,10 @@ def _compare_full(P, n, eta, ell, cells, dir_mode, sweeps, seed=1, chains_per_ce
 
 
 def test_serial_256_xy_lattice(P):
-    """One periodic cell, +x/+y chains from the lattice (exact distance ties)."""
+    """One periodic cell, +x/+y chains from the lattice (exact distance ties),
+    over the configuration's whole run of 200 sweeps."""
     w = inputs.WORKLOADS["serial_256"]
-    _compare_full(P, w["n"], w["eta"], w["ell"], 1, 0, 20)
+    _compare_full(P, w["n"], w["eta"], w["ell"], 1, 0, w["sweeps"])
 
 
 def test_periodic_isotropic_small(P):
@@ -284,9 +285,10 @@ def test_fp32_screen_matches_oracle(P, n, eta, cells, ell, sweeps):
 
 def test_fp32_screen_equals_fp64_at_full_size(P):
     """1M disks, eta 0.72, 64 x 64 cells: positions and per-sweep digests of the
-    screened form equal those of the FP64 form over several sweeps."""
+    screened form equal those of the FP64 form over 100 sweeps (about 2.6e10
+    events, each screened)."""
     w = inputs.WORKLOADS["pec_1m"]
-    sweeps = 3
+    sweeps = 100
     _say(f"[fp32] pec_1m: {sweeps} sweeps in each precision")
     out = []
     for prec in (0, 1):
