@@ -1936,7 +1936,6 @@ __global__ void k_zero_tallies(const Dev* __restrict__ ds) {
   }
 }
 
-// The sweep counter every kernel of the next sweep reads (one thread per system).
 // ---------------------------------------------------------------------------
 // One periodic cell (C = 1) with a bin grid: the same events as k_periodic,
 // found in an 8 x 8-bin window around the moving disk as in the walled cells.
@@ -1950,7 +1949,10 @@ __global__ void k_zero_tallies(const Dev* __restrict__ ds) {
 // reach is below the free-flight cap L/2 - sigma, so a window event is never
 // a pseudo event.  Every other event (a longer flight, the chain end, the
 // cap) is decided as in k_periodic, over every slot when the window cannot
-// vouch.  Event records are kept in the lanes and hashed 64 at a time.
+// vouch.  Plain lifts (the nearest disk in the window hit within the
+// remaining length, the cap and the window's reach) run in an inner loop, as
+// in the walled cells.  Event records are kept in the lanes and hashed 64 at
+// a time; the lifts are counted from them.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds) {
   const Dev& d = ds[blockIdx.y];
@@ -2023,16 +2025,18 @@ __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds
   const double eps = 1e-9 * sigma;
   const double reach = 5.0 * b - sigma - eps;
   const uint32_t pseudo_id = (uint32_t)d.n + 2, end_id = (uint32_t)d.n + 3;
-  // one event record; the records are hashed 64 at a time
-  auto record = [&](int kind, uint32_t id, double step) __attribute__((always_inline)) {
-    const uint64_t sb = (uint64_t)__double_as_longlong(step);
-    writelane3(rec_lo, rec_hi, rec_tag, (uint32_t)sb, (uint32_t)(sb >> 32),
-               ((uint32_t)kind << 29) | id, n_ring);
-    if (++n_ring == kDigestBatch) {
-      h ^= digest_batch_ids(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first);
-      ring_first += kDigestBatch;
-      n_ring = 0;
-    }
+  // the records are hashed 64 at a time; lifts are counted from the records
+  auto flush = [&]() __attribute__((always_inline)) {
+    h ^= digest_batch_ids(rec_lo, rec_hi, rec_tag, lane, kDigestBatch, ring_first);
+    n_lift += count_lifts(rec_tag, lane, kDigestBatch);
+    ring_first += kDigestBatch;
+    n_ring = 0;
+  };
+  // a coordinate moved across the box edge comes back from the other side
+  // (both candidates formed first, so that no lane branches)
+  auto wrap_box = [&](double v) __attribute__((always_inline)) {
+    const double vm = v - L, vp = v + L;
+    return v >= L ? vm : (v < 0.0 ? vp : v);
   };
 
   for (int64_t k = 0; k < n_m; ++k) {
@@ -2054,27 +2058,117 @@ __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds
     const double rx_ = dx != 0.0 ? 1.0 / dx : 1.0, ry_ = dy != 0.0 ? 1.0 / dy : 1.0;
     const double dsafe = reach * fmin(fabs(rx_), fabs(ry_));
     const int offx = dx < 0.0 ? -5 : -2, offy = dy < 0.0 ? -5 : -2;  // window origin
-    double rem = d.ell;
-    int a_slot = uniform_i32(slot_of[a]);
-    double ax = pos[a_slot].x, ay = pos[a_slot].y;
-    int64_t n_events = 0;
-    for (;;) {
-      if (++n_events > kMaxEventsPerChain) {
-        if (lane == 0) atomicOr(d.err, ERR_EVENT_CAP);
-        break;
-      }
-      // the 8 x 8-bin window, wrapped around the box
-      int abx, aby;
-      aby = (int)(((uint32_t)a_slot * inv_n20) >> 20);
-      abx = a_slot - aby * nb;
-      int wx = abx + offx + lx, wy = aby + offy + ly;
+    // this lane's slot in the 8 x 8-bin window around the bin of `slot`,
+    // wrapped around the box
+    auto window_slot = [&](int slot) __attribute__((always_inline)) {
+      const int by = (int)(((uint32_t)slot * inv_n20) >> 20);
+      const int bx = slot - by * nb;
+      int wx = bx + offx + lx, wy = by + offy + ly;
       wx += wx < 0 ? nb : 0;
       wx -= wx >= nb ? nb : 0;
       wy += wy < 0 ? nb : 0;
       wy -= wy >= nb ? nb : 0;
-      const int wsl = wy * nb + wx;
-      const double2 p = pos[wsl];
-      const uint32_t m = meta[wsl];
+      return wy * nb + wx;
+    };
+    double rem = d.ell;
+    int a_slot = uniform_i32(slot_of[a]);
+    double ax = pos[a_slot].x, ay = pos[a_slot].y;
+    // the event cap is held at the digest flushes: ring_first - ev0 is the
+    // chain's event count there, so a chain makes at most
+    // kMaxEventsPerChain + 63 events before it stops with the error
+    const uint64_t ev0 = ring_first + (uint64_t)n_ring;
+    int capped = 0;
+    int wsl = window_slot(a_slot);
+    double2 p = pos[wsl];
+    uint32_t m = meta[wsl];
+    for (;;) {
+      // One plain lift: the nearest disk in the window is hit within the
+      // remaining length, within the flight cap and within the reach the
+      // window vouches for.  That is exactly the full decision below finding
+      // a lift; every other event (no disk in the window, the chain end, a
+      // pseudo event, a flight the window cannot vouch for) is left to it,
+      // with nothing changed.  Every lane makes the test, moves the mover
+      // onto its own candidate and forms that move's pressure term while
+      // the wave minimum forms; the winner's values are the event's.  False
+      // on any other event, and at a flush that finds the event cap reached.
+      auto plain_event = [&]() __attribute__((always_inline)) -> bool {
+        const double rx = min_image(p.x - ax), ry = min_image(p.y - ay);
+        double s = 0.0;
+        const bool valid = contact(rx, ry, dx, dy, sig2, s);  // the mover's own slot: no contact
+        double nxl, nyl;
+        int plain_l, ns_l;
+        {
+          nxl = wrap_box(fma(s, dx, ax));
+          nyl = wrap_box(fma(s, dy, ay));
+          ns_l = bin_of(nyl) * nb + bin_of(nxl);
+          plain_l = (int)(s <= dsafe) & (int)(s < rem) & (int)(s <= cap);
+          // keep them here, beside the wave minimum
+          asm volatile("" : : "v"(plain_l), "v"(ns_l));
+        }
+        const unsigned key = argmin_key(s, valid);
+        const unsigned key_min = wave_min_u32(key);
+        if (__builtin_expect(key_min == 0xFFFFFFFFu, 0)) return false;
+        const int wl = argmin_lane(s, m, key, key_min);
+        if (__builtin_expect(readlane_i32(plain_l, wl) == 0, 0)) return false;
+        const double best_s = readlane_f64(s, wl);
+        const int bj = readlane_i32((int)m, wl);
+        const int bslot = readlane_i32(wsl, wl);
+        const double wpx = readlane_f64(p.x, wl), wpy = readlane_f64(p.y, wl);
+        const int ns = readlane_i32(ns_l, wl);
+        {
+          const uint64_t sb = (uint64_t)__double_as_longlong(best_s);
+          writelane3(rec_lo, rec_hi, rec_tag, (uint32_t)sb, (uint32_t)(sb >> 32),
+                     ((uint32_t)EV_LIFT << 29) | (uint32_t)bj, n_ring);
+        }
+        // the winning lane stores the moved centre
+        {
+          double2* const dst = (lane == wl) ? pos + a_slot : sink;
+          *dst = make_double2(nxl, nyl);
+        }
+        if (__builtin_expect(ns != a_slot, 0)) {
+          // the centre crossed into another bin, which is empty (a bin holds
+          // one centre): the winning lane stores it there, another lane
+          // empties the old slot (over the store above: LDS stores of a wave
+          // land in order), and lanes 0, 1, 2 move the meta words and the
+          // disk's slot in one store
+          const int other = wl == 0 ? 1 : 0;
+          double2* const dst = (lane == wl) ? pos + ns : ((lane == other) ? pos + a_slot : sink);
+          *dst = (lane == wl) ? make_double2(nxl, nyl) : nan2;
+          uint32_t* const dm = (lane == 0) ? meta + a_slot
+                                           : ((lane == 1) ? meta + ns
+                                                          : ((lane == 2) ? (uint32_t*)(slot_of + a) : sink32));
+          *dm = (lane == 0) ? kEmptySlot : ((lane == 1) ? (uint32_t)a : (uint32_t)ns);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // the next window is read while the pressure term forms (from the
+        // lane's own disk and moved centre, the values of this window)
+        const double ox = p.x, oy = p.y;
+        wsl = window_slot(bslot);
+        p = pos[wsl];
+        m = meta[wsl];
+        const double tx = min_image(ox - nxl), ty = min_image(oy - nyl);
+        acc = acc + readlane_f64(fma(tx, dx, ty * dy), wl);
+        rem = rem - best_s;
+        a = bj;
+        a_slot = bslot;
+        ax = wpx;
+        ay = wpy;
+        if (__builtin_expect(++n_ring == kDigestBatch, 0)) {
+          flush();
+          capped = (ring_first - ev0 >= (uint64_t)kMaxEventsPerChain) ? 1 : 0;
+          if (capped != 0) return false;
+        }
+        return true;
+      };
+      for (;;) {
+        if (__builtin_expect(!plain_event(), 0)) break;
+        if (__builtin_expect(!plain_event(), 0)) break;
+      }  // plain lifts
+      if (capped != 0) {
+        if (lane == 0) atomicOr(d.err, ERR_EVENT_CAP);
+        break;
+      }
+      // the full decision, on the window already read
       const double rx = min_image(p.x - ax), ry = min_image(p.y - ay);
       double s = 0.0;
       const bool valid = contact(rx, ry, dx, dy, sig2, s);  // the mover's own slot: no contact
@@ -2120,10 +2214,13 @@ __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds
       const double lim = best_s < rem ? best_s : rem;
       const int kind = uniform_i32(lim > cap ? EV_PSEUDO : (!(best_s < rem) ? EV_END : EV_LIFT));
       const double step = kind == EV_PSEUDO ? cap : (kind == EV_END ? rem : best_s);
-      record(kind, kind == EV_PSEUDO ? pseudo_id : (kind == EV_END ? end_id : (uint32_t)bj), step);
-      double nax = fma(step, dx, ax), nay = fma(step, dy, ay);
-      if (nax >= L) nax -= L; else if (nax < 0.0) nax += L;
-      if (nay >= L) nay -= L; else if (nay < 0.0) nay += L;
+      {
+        const uint32_t id = kind == EV_PSEUDO ? pseudo_id : (kind == EV_END ? end_id : (uint32_t)bj);
+        const uint64_t sb = (uint64_t)__double_as_longlong(step);
+        writelane3(rec_lo, rec_hi, rec_tag, (uint32_t)sb, (uint32_t)(sb >> 32),
+                   ((uint32_t)kind << 29) | id, n_ring);
+      }
+      const double nax = wrap_box(fma(step, dx, ax)), nay = wrap_box(fma(step, dy, ay));
       // store the moved disk (lane 0) and move it to another bin if it crossed
       // one (lane 0 empties the old slot, lane 1 fills the new one, which is
       // empty: a bin holds one centre)
@@ -2141,28 +2238,37 @@ __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds
         a_slot = ns;
       }
       wave_sync();
+      if (++n_ring == kDigestBatch) {
+        flush();
+        capped = (ring_first - ev0 >= (uint64_t)kMaxEventsPerChain) ? 1 : 0;
+      }
       if (kind == EV_END) break;
       if (kind == EV_PSEUDO) {
         rem = rem - cap;
         n_pseudo += 1;
         ax = nax;
         ay = nay;
-        continue;
+      } else {
+        rem = rem - best_s;
+        const double tx = min_image(wpx - nax), ty = min_image(wpy - nay);
+        acc = acc + fma(tx, dx, ty * dy);
+        a = bj;
+        a_slot = bslot;
+        ax = wpx;
+        ay = wpy;
       }
-      rem = rem - best_s;
-      double tx = wpx - nax, ty = wpy - nay;
-      if (tx < -half_L) tx += L; else if (tx >= half_L) tx -= L;
-      if (ty < -half_L) ty += L; else if (ty >= half_L) ty -= L;
-      acc = acc + fma(tx, dx, ty * dy);
-      n_lift += 1;
-      a = bj;
-      a_slot = bslot;
-      ax = wpx;
-      ay = wpy;
+      if (capped != 0) {
+        if (lane == 0) atomicOr(d.err, ERR_EVENT_CAP);
+        break;
+      }
+      wsl = window_slot(a_slot);
+      p = pos[wsl];
+      m = meta[wsl];
     }
   }
   wave_sync();
   h ^= digest_batch_ids(rec_lo, rec_hi, rec_tag, lane, n_ring, ring_first);
+  n_lift += count_lifts(rec_tag, lane, n_ring);
   for (int i = lane; i < n; i += 64) {
     const double2 v = pos[slot_of[i]];
     d.x[i] = v.x;
@@ -2178,6 +2284,7 @@ __global__ void __launch_bounds__(64) k_periodic_bins(const Dev* __restrict__ ds
   }
 }
 
+// The sweep counter every kernel of the next sweep reads (one thread per system).
 __global__ void k_sweep_done(const Dev* __restrict__ ds) {
   if (threadIdx.x == 0) *ds[blockIdx.y].sweep_ctr += 1;
 }
