@@ -141,7 +141,9 @@ typedef struct {
   int32_t  precision;       /* ec_precision                                                 */
   int32_t  start_mode;      /* ec_start_mode                                                */
   int32_t  cells_per_block; /* schedule only: simulation cells per workgroup (1, 2, 4);     
-                               0 = 4 when four cells' LDS fits 160 KiB, else 1              */
+                               0 = 1 where a colour phase has no more cells than the
+                               device has CUs, else 4 when four cells' LDS fits 160 KiB,
+                               else 1                                                       */
   double   screen_margin;   /* relative guard band of EC_PREC_FP32_SCREEN, 0 = 1e-5         */
   uint64_t seed;            /* Philox4x64-10 key word                                       */
   uint32_t system;          /* index of the system inside a batch (second key-word part)    */

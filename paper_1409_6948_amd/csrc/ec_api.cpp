@@ -493,6 +493,20 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
 
 extern "C" {
 
+// Default cells per workgroup of a system swept alone, on the current device:
+// where a colour phase has no more cells than the device has CUs, one cell
+// per workgroup, so that each wavefront has a CU of its own (measured about
+// 2 % faster at 64 cells per phase than four wavefronts sharing a CU); else
+// the choice of validate().  An explicit cells_per_block is kept.
+static void default_cells_per_block(const ec_params* p, Derived* dv) {
+  if (p->cells_per_block != 0 || p->cells_per_side <= 1 || (p->flags & EC_FLAG_STRIPES)) return;
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return;
+  const int64_t half = p->cells_per_side / 2;
+  if (half * half <= (int64_t)n_cu) dv->cpb = 1;
+}
+
 ec_status ec_init_system(const ec_params* p, void* ws, size_t ws_bytes, void* stream,
                          ec_system* out) {
   if (!out || !ws) return EC_E_INVALID;
@@ -501,6 +515,7 @@ ec_status ec_init_system(const ec_params* p, void* ws, size_t ws_bytes, void* st
   std::string why;
   ec_status st = validate(p, &dv, &why);
   if (st != EC_OK) return st;
+  default_cells_per_block(p, &dv);
   return init_system_at(p, dv, (unsigned char*)ws, ws_bytes, (hipStream_t)stream, false, out);
 }
 
@@ -1322,6 +1337,7 @@ ec_status ec_sweep_static(const ec_params* p, double* x, double* y, int64_t firs
   std::string why;
   ec_status st = validate(p, &dv, &why);
   if (st != EC_OK) return st;
+  default_cells_per_block(p, &dv);
   if (p->n_disks > ec::kStaticMaxDisks) return EC_E_NOMEM;
   const Layout lay = make_layout(p->n_disks, p->cells_per_side, p->chains_per_cell, true);
   if (lay.total > ec::kStaticScratchBytes) return EC_E_NOMEM;
