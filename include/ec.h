@@ -20,8 +20,8 @@
  * Every call returns ec_status (EC_OK = 0).  No exception crosses the ABI.
  *
  * Memory: the caller allocates one device buffer of ec_workspace_bytes()
- * bytes (for instance a torch uint8 tensor) and keeps it alive until
- * ec_destroy.  The library allocates no device memory.  The host handle is
+ * bytes, 256-byte aligned (for instance a torch uint8 tensor, whose device
+ * allocations are), and keeps it alive until ec_destroy.  The library allocates no device memory.  The host handle is
  * created by ec_init_system and freed by ec_destroy.  Host arrays passed to
  * the get/set calls belong to the caller.
  *
@@ -158,10 +158,10 @@ ec_status ec_workspace_bytes(const ec_params* p, size_t* bytes);
 
 /* Create a system: validates p, lays out the workspace, places the disks on
  * the k x k start lattice (odd rows shifted by half a spacing) and clears the
- * tallies.  dev_workspace: device pointer, ws_bytes >= ec_workspace_bytes().
- * hip_stream: hipStream_t (borrowed; NULL = null stream).
- * Errors: EC_E_INVALID (bad parameters, including N not an even square),
- * EC_E_NOMEM (workspace too small), EC_E_HIP. */
+ * tallies.  dev_workspace: device pointer, 256-byte aligned, ws_bytes >=
+ * ec_workspace_bytes().  hip_stream: hipStream_t (borrowed; NULL = null
+ * stream).  Errors: EC_E_INVALID (bad parameters, or a workspace that is not
+ * 256-byte aligned), EC_E_NOMEM (workspace too small), EC_E_HIP. */
 ec_status ec_init_system(const ec_params* p, void* dev_workspace, size_t ws_bytes,
                          void* hip_stream, ec_system* out);
 
@@ -341,8 +341,8 @@ typedef struct ec_batch_s* ec_batch;
  * system (C = 1), or n_sys outside [1, 4096]. */
 ec_status ec_batch_workspace_bytes(const ec_params* ps, int32_t n_sys, size_t* bytes);
 
-/* Create the batch in dev_workspace (caller-owned, >= ec_batch_workspace_bytes)
- * on hip_stream (borrowed).  Each system starts from its lattice as in
+/* Create the batch in dev_workspace (caller-owned, 256-byte aligned (else
+ * EC_E_INVALID), >= ec_batch_workspace_bytes) on hip_stream (borrowed).  Each system starts from its lattice as in
  * ec_init_system; ps[i].cells_per_block is ignored (the batch schedule
  * applies, initially 1).  Synchronises. */
 ec_status ec_init_batch(const ec_params* ps, int32_t n_sys, void* dev_workspace, size_t ws_bytes,

@@ -437,6 +437,20 @@ void fill_record(ec::Dev* out, const ec_params* p, const Derived& dv, unsigned c
   d.system = p->system;
 }
 
+// Default cells per workgroup of a system swept alone, on the current device:
+// where a colour phase has no more cells than the device has CUs, one cell
+// per workgroup, so that each wavefront has a CU of its own (measured about
+// 2 % faster at 64 cells per phase than four wavefronts sharing a CU); else
+// the choice of validate().  An explicit cells_per_block is kept.
+static void default_cells_per_block(const ec_params* p, Derived* dv) {
+  if (p->cells_per_block != 0 || p->cells_per_side <= 1 || (p->flags & EC_FLAG_STRIPES)) return;
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return;
+  const int64_t half = p->cells_per_side / 2;
+  if (half * half <= (int64_t)n_cu) dv->cpb = 1;
+}
+
 // Create a system in a workspace region (validated parameters); with a
 // batch owner the handle is a view that the batch destroys.
 ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b, size_t ws_bytes,
@@ -447,6 +461,7 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   if (!s) return EC_E_NOMEM;
   s->p = *p;
   s->dv = dv;
+  if (!in_batch) default_cells_per_block(p, &s->dv);
   s->lay = lay;
   s->stream = stream;
   s->in_batch = in_batch;
@@ -458,7 +473,7 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
   s->gr_rmax = 0.0;
   s->gr_bins = 0;
   s->gr_samples = 0;
-  fill_record(&s->dev, p, dv, b, lay);
+  fill_record(&s->dev, p, s->dv, b, lay);
   ec::Dev& d = s->dev;
   s->dev_d = (ec::Dev*)(b + lay.dev);
   s->shape = shape_of(d, *p);
@@ -493,29 +508,15 @@ ec_status init_system_at(const ec_params* p, const Derived& dv, unsigned char* b
 
 extern "C" {
 
-// Default cells per workgroup of a system swept alone, on the current device:
-// where a colour phase has no more cells than the device has CUs, one cell
-// per workgroup, so that each wavefront has a CU of its own (measured about
-// 2 % faster at 64 cells per phase than four wavefronts sharing a CU); else
-// the choice of validate().  An explicit cells_per_block is kept.
-static void default_cells_per_block(const ec_params* p, Derived* dv) {
-  if (p->cells_per_block != 0 || p->cells_per_side <= 1 || (p->flags & EC_FLAG_STRIPES)) return;
-  int dev = 0, n_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return;
-  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return;
-  const int64_t half = p->cells_per_side / 2;
-  if (half * half <= (int64_t)n_cu) dv->cpb = 1;
-}
-
 ec_status ec_init_system(const ec_params* p, void* ws, size_t ws_bytes, void* stream,
                          ec_system* out) {
   if (!out || !ws) return EC_E_INVALID;
+  if (((uintptr_t)ws & 255) != 0) return EC_E_INVALID;  // the layout's arrays are 256-byte aligned
   *out = nullptr;
   Derived dv;
   std::string why;
   ec_status st = validate(p, &dv, &why);
   if (st != EC_OK) return st;
-  default_cells_per_block(p, &dv);
   return init_system_at(p, dv, (unsigned char*)ws, ws_bytes, (hipStream_t)stream, false, out);
 }
 
@@ -1150,6 +1151,7 @@ ec_status ec_batch_workspace_bytes(const ec_params* ps, int32_t n_sys, size_t* b
 ec_status ec_init_batch(const ec_params* ps, int32_t n_sys, void* ws, size_t ws_bytes, void* stream,
                         ec_batch* out) {
   if (!out || !ws) return EC_E_INVALID;
+  if (((uintptr_t)ws & 255) != 0) return EC_E_INVALID;  // the layout's arrays are 256-byte aligned
   *out = nullptr;
   BatchLayout bl;
   std::vector<Derived> dvs;

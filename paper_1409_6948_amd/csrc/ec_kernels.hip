@@ -474,37 +474,92 @@ __global__ void k_count(const Dev* __restrict__ ds, int squares) {
   }
   d.cell_of[i] = c;
   d.reg_of[i] = (uint8_t)r;
-  atomicAdd(&d.reg_count[kRegions * c + r], 1);
+  // one atomic per distinct (cell, region) of the wavefront: consecutive ids
+  // are mostly neighbours in space, so a wave's disks fall into a few cells
+  const int key = kRegions * c + r;
+  uint64_t todo = __builtin_amdgcn_ballot_w64(true);
+  while (todo) {
+    const int leader = (int)__builtin_ctzll(todo);
+    const int lk = __builtin_amdgcn_readlane(key, leader);
+    const uint64_t same = __builtin_amdgcn_ballot_w64(key == lk) & todo;
+    if ((threadIdx.x & 63) == (unsigned)leader) atomicAdd(&d.reg_count[lk], (int)__builtin_popcountll(same));
+    todo &= ~same;
+  }
 }
 
 // Exclusive prefix sum of the (cell, region) counts, one workgroup of 1024
-// threads; a cell's start is that of its first region.
+// threads; a cell's start is that of its first region.  The counts are
+// taken in tiles of 4,096, four consecutive counts per thread in one 16-byte
+// access (the count and start arrays are 256-byte aligned), summed in the
+// thread, then over the wave and over the 16 waves; the next tile's counts
+// are loaded while the current one is summed.
 __global__ void __launch_bounds__(1024) k_scan(const Dev* __restrict__ ds) {
   const Dev& d = ds[blockIdx.y];
-  __shared__ int32_t part[1024];
+  constexpr int kTile = 4096;
+  __shared__ int32_t wsum[16];
   const int ncell = d.C * d.C;
   const int nreg = kRegions * ncell;
-  int per = (nreg + 1023) / 1024;
-  int b0 = threadIdx.x * per;
-  int sum = 0;
-  for (int c = b0; c < b0 + per && c < nreg; ++c) sum += d.reg_count[c];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
+  const int t = (int)threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int32_t* __restrict__ cnt = d.reg_count;
+  int32_t* __restrict__ start = d.reg_start;
+  auto load = [&](int base) __attribute__((always_inline)) {
+    const int i0 = base + 4 * t;
+    int4 v;
+    if (i0 + 3 < nreg) {
+      v = *(const int4*)(cnt + i0);
+    } else {
+      v.x = (i0 < nreg) ? cnt[i0] : 0;
+      v.y = (i0 + 1 < nreg) ? cnt[i0 + 1] : 0;
+      v.z = (i0 + 2 < nreg) ? cnt[i0 + 2] : 0;
+      v.w = 0;
+    }
+    return v;
+  };
+  int4 v = load(0);
+  int carry = 0;
+  for (int base = 0; base < nreg; base += kTile) {
+    const int4 cur = v;
+    if (base + kTile < nreg) v = load(base + kTile);  // the next tile, in flight meanwhile
+    const int tot = cur.x + cur.y + cur.z + cur.w;
+    // inclusive sum of the thread totals over the wave
+    int x = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+    int woff = 0, tile_total = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      const int sw = wsum[w];
+      woff += (w < wave) ? sw : 0;
+      tile_total += sw;
+    }
+    const int e0 = carry + woff + (x - tot);
+    const int4 out = make_int4(e0, e0 + cur.x, e0 + cur.x + cur.y, e0 + cur.x + cur.y + cur.z);
+    const int i0 = base + 4 * t;
+    if (i0 + 3 < nreg) {
+      *(int4*)(start + i0) = out;
+    } else {
+      if (i0 < nreg) start[i0] = out.x;
+      if (i0 + 1 < nreg) start[i0 + 1] = out.y;
+      if (i0 + 2 < nreg) start[i0 + 2] = out.z;
+    }
+    // the cell starts: the one multiple of kRegions among the four, if any
+    const int r0 = i0 % kRegions;
+    const int k = (r0 == 0) ? 0 : kRegions - r0;
+    if (k < 4 && i0 + k < nreg) {
+      const int sv = (k == 0) ? out.x : ((k == 1) ? out.y : ((k == 2) ? out.z : out.w));
+      d.cell_start[(i0 + k) / kRegions] = sv;
+    }
+    carry += tile_total;
+    __syncthreads();  // every thread has read wsum before the next tile writes it
   }
-  int run = (threadIdx.x == 0) ? 0 : part[threadIdx.x - 1];
-  for (int c = b0; c < b0 + per && c < nreg; ++c) {
-    d.reg_start[c] = run;
-    if (c % kRegions == 0) d.cell_start[c / kRegions] = run;
-    run += d.reg_count[c];
-  }
-  if (threadIdx.x == 1023) {
-    d.reg_start[nreg] = part[1023];
-    d.cell_start[ncell] = part[1023];
+  if (t == 0) {
+    start[nreg] = carry;
+    d.cell_start[ncell] = carry;
   }
 }
 
@@ -513,7 +568,23 @@ __global__ void k_scatter(const Dev* __restrict__ ds) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   const int k = kRegions * d.cell_of[i] + (int)d.reg_of[i];
-  int slot = atomicAdd(&d.reg_fill[k], 1);
+  // one atomic per distinct (cell, region) of the wavefront; each lane's slot
+  // is the group's base plus its rank among the group's lanes (the order
+  // inside a region is free: staging sorts a cell's ids)
+  const int lane = (int)(threadIdx.x & 63);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint64_t todo = __builtin_amdgcn_ballot_w64(true);
+  int slot = 0;
+  while (todo) {
+    const int leader = (int)__builtin_ctzll(todo);
+    const int lk = __builtin_amdgcn_readlane(k, leader);
+    const uint64_t same = __builtin_amdgcn_ballot_w64(k == lk) & todo;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&d.reg_fill[lk], (int)__builtin_popcountll(same));
+    base = __builtin_amdgcn_readlane(base, leader);
+    if (k == lk) slot = base + (int)__builtin_popcountll(same & below);
+    todo &= ~same;
+  }
   d.cell_ids[d.reg_start[k] + slot] = (int32_t)i;
 }
 

@@ -103,6 +103,13 @@ def test_init_rejects_small_workspace_without_touching_gpu():
     assert st == E.EC_E_NOMEM and not h.value
     st = lib.ec_init_system(C.byref(p), None, 1 << 30, None, C.byref(h))
     assert st == E.EC_E_INVALID
+    # the workspace's arrays are laid out 256-byte aligned from its start
+    st = lib.ec_init_system(C.byref(p), C.c_void_p(0x1010), 1 << 30, None, C.byref(h))
+    assert st == E.EC_E_INVALID and not h.value
+    ps = (E.Params * 2)(P.make_params(4096, 0.70, 20.0, 8), P.make_params(4096, 0.60, 20.0, 8))
+    b = C.c_void_p()
+    st = lib.ec_init_batch(ps, 2, C.c_void_p(0x1010), 1 << 30, None, C.byref(b))
+    assert st == E.EC_E_INVALID and not b.value
 
 
 def test_batch_workspace_is_systems_plus_snapshot():
