@@ -1007,7 +1007,7 @@ def test_dependency_cone_replays_later_phases():
 
 
 # --------------------------------------------------------------------------
-# Striped decomposition with rejection (Sec. 3.4, Fig. 3 "stripes"; Sec. 4)
+# Striped decomposition with rejection (Sec. 3.4, the stripes variant of Fig. 3; Sec. 4)
 # --------------------------------------------------------------------------
 def _image(d, L):
     return d - L * np.round(d / L)
