@@ -21,9 +21,10 @@
  *
  * Memory: the caller allocates one device buffer of ec_workspace_bytes()
  * bytes, 256-byte aligned (for instance a torch uint8 tensor, whose device
- * allocations are), and keeps it alive until ec_destroy.  The library allocates no device memory.  The host handle is
- * created by ec_init_system and freed by ec_destroy.  Host arrays passed to
- * the get/set calls belong to the caller.
+ * allocations are), and keeps it alive until ec_destroy.  The library
+ * allocates no device memory.  The host handle is created by ec_init_system
+ * and freed by ec_destroy.  Host arrays passed to the get/set calls belong to
+ * the caller.
  *
  * Streams: every device operation is enqueued on the stream given at init
  * (a hipStream_t passed as void*, NULL = the null stream), in call order.
@@ -77,17 +78,17 @@ typedef enum {
 
 /* ec_params.flags */
 #define EC_FLAG_SCAN_SEARCH 1u  /* walled cells: search every staged disk for each event
-                                   instead of the 4x4-bin window (same events, slower)     */
+                                   instead of the 8x8-bin window (same events, slower)     */
 /* Schedule of the walled-cell sweep.  The results are identical either way
  * (same positions, digests and tallies); only the timing differs.
  *   one launch:    all four colour phases in one kernel launch, each cell
  *                  starting once its neighbours of earlier phases are done;
  *                  the default of a system swept alone.
  *   phase launches: one launch per colour phase, the launch boundary
- *                  separating the phases (Sec. 3.4 as written); the default
- *                  of a batch, whose waiting cells would otherwise hold
- *                  wavefront slots that other systems' cells can use.
- * Setting both bits is EC_E_INVALID; the systems of a batch share them. */
+ *                  separating the phases (Sec. 3.4 as written).
+ * A batch runs from a device ready queue unless one of these bits selects
+ * its initial schedule (EC_SCHEDULE_* below).  Setting both bits is
+ * EC_E_INVALID; the systems of a batch share them. */
 #define EC_FLAG_PHASE_LAUNCHES 2u
 #define EC_FLAG_ONE_LAUNCH 4u
 /* Rejection at the cell boundary (walled cells, FP64): a chain that would
@@ -110,7 +111,7 @@ typedef enum {
  * Sec. 3.4 step 4).  Costs one pass over the neighbour pairs per sweep. */
 #define EC_FLAG_CHECK_OVERLAP 16u
 /* The striped decomposition with rejection, the variant Sec. 3.4 compares
- * against (Fig. 3 "stripes"): cells_per_side stripes of width L/C > 2 sigma
+ * against (the stripes of Fig. 3): cells_per_side stripes of width L/C > 2 sigma
  * span the box, horizontal on even sweeps with chains along x, vertical on
  * odd sweeps with chains along y, each with a random sign (dir_mode must be
  * EC_DIR_XY); a random
@@ -126,8 +127,10 @@ typedef enum {
 typedef struct {
   uint32_t abi_version;     /* must equal EC_ABI_VERSION                                    */
   uint32_t flags;           /* EC_FLAG_* bits, 0 = default                                  */
-  int64_t  n_disks;         /* N; the lattice start needs N = k*k with k even; walled cells
-                               (C > 1) take N <= 2^29 - 4 (EC_E_UNSUPPORTED above)       */
+  int64_t  n_disks;         /* N; disk i starts on site (i mod k, i div k) of the k x k
+                               start lattice, k = ceil(sqrt N); walled cells (C > 1)
+                               take N <= 2^29 - 4, one periodic cell N <= 2048
+                               (EC_E_UNSUPPORTED above)                                  */
   double   sigma;           /* disk diameter, in [2^-300, 2^300]                            */
   double   eta;             /* 0 < eta < pi/(2 sqrt 3); L = sigma sqrt(N pi / (4 eta))       */
   double   ell;             /* displacement of one chain, > 0                               */
@@ -342,9 +345,10 @@ typedef struct ec_batch_s* ec_batch;
 ec_status ec_batch_workspace_bytes(const ec_params* ps, int32_t n_sys, size_t* bytes);
 
 /* Create the batch in dev_workspace (caller-owned, 256-byte aligned (else
- * EC_E_INVALID), >= ec_batch_workspace_bytes) on hip_stream (borrowed).  Each system starts from its lattice as in
- * ec_init_system; ps[i].cells_per_block is ignored (the batch schedule
- * applies, initially 1).  Synchronises. */
+ * EC_E_INVALID), >= ec_batch_workspace_bytes) on hip_stream (borrowed).
+ * Each system starts from its lattice as in ec_init_system;
+ * ps[i].cells_per_block is ignored (the batch schedule applies, initially
+ * 1).  Synchronises. */
 ec_status ec_init_batch(const ec_params* ps, int32_t n_sys, void* dev_workspace, size_t ws_bytes,
                         void* hip_stream, ec_batch* out);
 
