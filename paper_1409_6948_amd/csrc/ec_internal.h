@@ -117,7 +117,7 @@ struct Dev {
   int32_t C, nb, gridb, cap_own, chains_per_cell, dir_mode, start_mode, precision;
   int32_t pbins;  // one periodic cell: bins per side of its bin grid, 0 = brute-force search
   int32_t lds_per_cell, cells_per_block;
-  int32_t search;                   // 0: 4x4-bin window with guard; 1: scan of every slot
+  int32_t search;                   // 0: 8x8-bin window with guard; 1: scan of every slot
   int64_t dep_wait_ticks;           // one-launch sweep: limit of one wait, 100 MHz clock ticks
   int32_t reject;                   // 1: a chain reaching a wall or a frozen disk is undone
   int32_t check_overlap;            // 1: every sweep ends with a check of all neighbour pairs
