@@ -185,12 +185,16 @@ def main():
     ap.add_argument("--schedule", choices=("auto", "one-launch", "phase-launches"), default="auto",
                     help="all four colour phases of a sweep in one launch with per-cell "
                          "dependencies, or one launch per phase; auto = the library's default "
-                         "(one launch for a system alone, phase launches for a batch)")
+                         "(one launch for a system alone, a ready queue for a batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "fp32-screen"), default=None,
                     help="fp32-screen: FP32 screening of candidates, FP64 for the survivors "
                          "and every commit (identical events); default: the workload's own "
                          "(FP64 for pec_1m, FP32 screen for pec_16m and batch64)")
+    ap.add_argument("--other-precision", action="store_true",
+                    help="walled cells: also run the same sweeps from the same start in the "
+                         "other precision (FP64 or FP32 screen), compare the per-sweep digests "
+                         "and report its time")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -266,6 +270,7 @@ def main():
     count_ms, scatter_ms, rebins = g.get_rebin_timing()
     g.set_timing(False)
     z, bp, counts = g.measure_pressure()
+    digests = g.get_digests(args.warmup + args.steps) if args.warmup + args.steps <= 1024 else None
     psi = None
     if w.get("psi6"):
         psi6, nb = g.measure_psi6()
@@ -348,6 +353,36 @@ def main():
         "latency_bound": latency,
         "rebin": rebin,
     }
+    if w["cells"] > 1 and args.other_precision and digests is not None:
+        # the same sweeps from the same start in the other form; identical
+        # collision sequences give identical per-sweep digests
+        g.close()
+        other = "fp64" if precision == "fp32-screen" else "fp32-screen"
+        po = P.make_params(w["n"], w["eta"], w["ell"], w["cells"], dir_mode=w["dir_mode"],
+                           seed=w["seed"], cells_per_block=args.cells_per_block,
+                           precision=P.EC_PREC_FP64 if other == "fp64" else P.EC_PREC_FP32_SCREEN,
+                           flags=flags)
+        print(f"# the same sweeps in {other}", file=sys.stderr, flush=True)
+        go = P.System(po, device="cuda:0")
+        go.sweep(args.warmup)
+        torch.cuda.synchronize()
+        go.reset_tallies()
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record(go.stream)
+        go.sweep(args.steps)
+        f1.record(go.stream)
+        torch.cuda.synchronize()
+        ms_o = f0.elapsed_time(f1) / args.steps
+        dig_o = go.get_digests(args.warmup + args.steps)
+        _, _, counts_o = go.measure_pressure()
+        go.close()
+        line["other_precision"] = {
+            "precision": other, "ms_per_step": ms_o,
+            "value": counts_o["lifts"] / (ms_o * args.steps / 1e3),
+            "sweeps_compared": args.warmup + args.steps,
+            "digests_identical": bool(np.array_equal(digests, dig_o)),
+            "speedup_of_this_precision": ms_o / (gpu_ms / args.steps)}
     if not args.no_cpu_baseline:
         print("# CPU oracle baseline (phase-parallel)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)
